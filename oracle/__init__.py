@@ -1,0 +1,249 @@
+"""Oracle for the convolution extractors — TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package. It shares no code with the GPU library (``paper_2402_09481_amd``)
+and never imports it.
+
+What it computes is the plain definition of each extractor as a GF(2)
+matrix-vector product (see ``oracle.c`` for the formulas and the passages they
+follow), plus its own primality / primitive-root utilities written from the
+definition of a prime with 2 as a primitive root. Preconditions follow the
+paper: Toeplitz needs 1 <= m <= n; Circulant needs n = n_in + 1 prime with
+primitive root 2 and 1 <= m <= n - 1 (full row rank bound of the Circulant
+proof); Dodis et al. needs n prime with primitive root 2, 1 <= m <= n and
+x not all-zero and not all-one (precondition stated with the Dodis
+implementation). On a failed precondition the functions return the error code
+and no output.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+OK = 0
+EINVAL = -1
+ENOTNA = -2
+EDEGENERATE = -3
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc into liboracle.so next to it."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        u64 = ctypes.c_uint64
+        lib.oracle_toeplitz_bits.argtypes = [u64p, u64, u64p, u64, ctypes.c_int, u64p]
+        lib.oracle_dodis_bits.argtypes = [u64p, u64p, u64, u64, u64p]
+        lib.oracle_circulant_bits.argtypes = [u64p, u64, u64p, u64, u64p]
+        lib.oracle_toeplitz_rows.argtypes = [u64p, u64, u64p, u64, ctypes.c_int, u64, u64, u64p]
+        lib.oracle_dodis_rows.argtypes = [u64p, u64p, u64, u64, u64, u64p]
+        lib.oracle_circulant_rows.argtypes = [u64p, u64, u64p, u64, u64, u64p]
+        for f in (lib.oracle_toeplitz_bits, lib.oracle_dodis_bits, lib.oracle_circulant_bits,
+                  lib.oracle_toeplitz_rows, lib.oracle_dodis_rows, lib.oracle_circulant_rows):
+            f.restype = None
+        _lib = lib
+    return _lib
+
+
+def _nw(nbits: int) -> int:
+    return (int(nbits) + 63) >> 6
+
+
+def _masked(words, nbits: int) -> np.ndarray:
+    """Copy of the first ceil(nbits/64) words with bits >= nbits cleared (inputs'
+    tail bits are ignored), plus one spare zero word."""
+    w = np.zeros(_nw(nbits) + 1, dtype=np.uint64)
+    src = np.asarray(words, dtype=np.uint64)[: _nw(nbits)]
+    w[: src.size] = src
+    r = int(nbits) & 63
+    if r:
+        w[_nw(nbits) - 1] &= np.uint64((1 << r) - 1)
+    return w
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+# ------------------------------------------------------------------ primes with primitive root 2
+
+def is_prime(v: int) -> bool:
+    """Trial division by 2, 3 and 6k +- 1 up to sqrt(v)."""
+    v = int(v)
+    if v < 2:
+        return False
+    if v < 4:
+        return True
+    if v % 2 == 0 or v % 3 == 0:
+        return False
+    d = 5
+    while d * d <= v:
+        if v % d == 0 or v % (d + 2) == 0:
+            return False
+        d += 6
+    return True
+
+
+def prime_factors(v: int):
+    """Distinct prime factors of v by trial division."""
+    v = int(v)
+    out = []
+    d = 2
+    while d * d <= v:
+        if v % d == 0:
+            out.append(d)
+            while v % d == 0:
+                v //= d
+        d += 1 if d == 2 else 2
+    if v > 1:
+        out.append(v)
+    return out
+
+
+def is_na_prime(n: int) -> bool:
+    """n is prime and 2 generates the multiplicative group mod n, i.e. the order of
+    2 mod n is n - 1: 2^((n-1)/q) != 1 mod n for every prime q dividing n - 1."""
+    n = int(n)
+    if n == 2:
+        return False  # the group mod 2 is trivial; 2 is not a unit
+    if not is_prime(n):
+        return False
+    return all(pow(2, (n - 1) // q, n) != 1 for q in prime_factors(n - 1))
+
+
+def next_na(v: int) -> int:
+    """Smallest prime >= v with primitive root 2."""
+    c = max(int(v), 3)
+    while not is_na_prime(c):
+        c += 1
+    return c
+
+
+def prev_na(v: int) -> int:
+    """Largest prime <= v with primitive root 2 (0 if none)."""
+    c = int(v)
+    while c >= 3 and not is_na_prime(c):
+        c -= 1
+    return c if c >= 3 else 0
+
+
+def closest_na(v: int) -> int:
+    """Prime with primitive root 2 nearest to v; on a tie the smaller one."""
+    up, lo = next_na(v), prev_na(v)
+    if lo == 0:
+        return up
+    return lo if (int(v) - lo) <= (up - int(v)) else up
+
+
+# ------------------------------------------------------------------ preconditions
+
+def check(kind: str, n: int, m: int, x=None) -> int:
+    n, m = int(n), int(m)
+    if kind == "toeplitz":
+        return OK if (n >= 1 and 1 <= m <= n) else EINVAL
+    if kind == "circulant":
+        if n < 1 or m < 1 or m > n:  # m <= (n+1) - 1
+            return EINVAL
+        return OK if is_na_prime(n + 1) else ENOTNA
+    if kind == "dodis":
+        if n < 1 or m < 1 or m > n:
+            return EINVAL
+        if not is_na_prime(n):
+            return ENOTNA
+        if x is not None:
+            w = _masked(x, n)[: _nw(n)]
+            ones = sum(int(v).bit_count() for v in w)
+            if ones == 0 or ones == n:
+                return EDEGENERATE
+        return OK
+    return EINVAL
+
+
+# ------------------------------------------------------------------ extractors (whole output)
+
+def toeplitz(x, y, n: int, m: int, seed_order: str = "paper"):
+    """(code, z): z packed m bits, from the bit-by-bit definition."""
+    code = check("toeplitz", n, m)
+    if code:
+        return code, None
+    z = np.zeros(_nw(m) + 1, np.uint64)
+    xx, yy = _masked(x, n), _masked(y, n + m - 1)
+    _load().oracle_toeplitz_bits(_p(xx), n, _p(yy), m, int(seed_order == "linear"), _p(z))
+    return OK, z[: _nw(m)]
+
+
+def circulant(x, y, n_in: int, m: int):
+    code = check("circulant", n_in, m)
+    if code:
+        return code, None
+    z = np.zeros(_nw(m) + 1, np.uint64)
+    xx, yy = _masked(x, n_in), _masked(y, n_in + 1)
+    _load().oracle_circulant_bits(_p(xx), n_in, _p(yy), m, _p(z))
+    return OK, z[: _nw(m)]
+
+
+def dodis(x, y, n: int, m: int):
+    code = check("dodis", n, m, x)
+    if code:
+        return code, None
+    z = np.zeros(_nw(m) + 1, np.uint64)
+    xx, yy = _masked(x, n), _masked(y, n)
+    _load().oracle_dodis_bits(_p(xx), _p(yy), n, m, _p(z))
+    return OK, z[: _nw(m)]
+
+
+# ------------------------------------------------------------------ selected rows, 64 terms per step
+
+def toeplitz_rows(x, y, n: int, m: int, i0: int, cnt: int, seed_order: str = "paper") -> np.ndarray:
+    """Packed z_{i0} .. z_{i0+cnt-1} (bit r of the result is z_{i0+r})."""
+    assert check("toeplitz", n, m) == OK and 0 <= i0 and i0 + cnt <= m
+    out = np.zeros(_nw(cnt) + 1, np.uint64)
+    xx, yy = _masked(x, n), _masked(y, n + m - 1)
+    _load().oracle_toeplitz_rows(_p(xx), n, _p(yy), m, int(seed_order == "linear"), i0, cnt, _p(out))
+    return out[: _nw(cnt)]
+
+
+def circulant_rows(x, y, n_in: int, m: int, i0: int, cnt: int) -> np.ndarray:
+    assert check("circulant", n_in, m) == OK and 0 <= i0 and i0 + cnt <= m
+    out = np.zeros(_nw(cnt) + 1, np.uint64)
+    xx, yy = _masked(x, n_in), _masked(y, n_in + 1)
+    _load().oracle_circulant_rows(_p(xx), n_in, _p(yy), i0, cnt, _p(out))
+    return out[: _nw(cnt)]
+
+
+def dodis_rows(x, y, n: int, m: int, i0: int, cnt: int) -> np.ndarray:
+    assert check("dodis", n, m, x) == OK and 0 <= i0 and i0 + cnt <= m
+    out = np.zeros(_nw(cnt) + 1, np.uint64)
+    xx, yy = _masked(x, n), _masked(y, n)
+    _load().oracle_dodis_rows(_p(xx), _p(yy), n, i0, cnt, _p(out))
+    return out[: _nw(cnt)]
+
+
+def extract(kind: str, x, y, n: int, m: int, seed_order: str = "paper", packed: bool = True):
+    """Whole output via the packed row routine (fast enough up to n ~ 2^22).
+    Returns (code, z)."""
+    code = check(kind, n, m, x if kind == "dodis" else None)
+    if code:
+        return code, None
+    if kind == "toeplitz":
+        return OK, toeplitz_rows(x, y, n, m, 0, m, seed_order)
+    if kind == "circulant":
+        return OK, circulant_rows(x, y, n, m, 0, m)
+    return OK, dodis_rows(x, y, n, m, 0, m)
