@@ -1,0 +1,181 @@
+/*
+ * extractor.h — C-ABI of the MI355X convolution-extractor library
+ * (Toeplitz, Circulant and Dodis et al. randomness extractors, computed
+ * exactly as an integer convolution by a number-theoretic transform modulo an
+ * NTT-friendly prime, reduced mod 2 and truncated).
+ *
+ * Paper: "Cryptomite: a versatile and user-friendly library of randomness
+ * extractors", arXiv 2402.09481.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Bit strings are packed little-endian uint64 words: bit i is
+ * (w[i >> 6] >> (i & 63)) & 1. Input bits beyond a string's length are
+ * ignored; output bits of z beyond m are written as 0.
+ *
+ * x, y, z are DEVICE pointers, owned by the caller, on the context's device.
+ * Inputs are read-only. z must not overlap x or y (EXT_EINVAL otherwise).
+ *
+ * Every extraction call is stream-ordered and asynchronous: it validates its
+ * arguments on the host, synchronously, then enqueues GPU work on `stream`
+ * (a hipStream_t, NULL = the default stream) and returns. z is valid once
+ * that stream has reached the end of the enqueued work. With EXT_SYNC the
+ * call waits for the stream itself and returns the device-side status.
+ *
+ * Return values: 0 = enqueued (or done, with EXT_SYNC); a negative EXT_E*
+ * code otherwise. On any host-side error nothing is enqueued and z is not
+ * touched. The one data-dependent check (Dodis et al.: x must not be all
+ * zeros or all ones) runs on the device: z is zero-filled and the code
+ * EXT_EDEGENERATE is written to *status (if status is not NULL; a device or
+ * host-pinned int32) — and returned, with EXT_SYNC.
+ *
+ * The library keeps device workspace in a stream-ordered pool bounded by the
+ * context's HBM budget; a call whose workspace does not fit returns
+ * EXT_ENOMEM without enqueuing anything. Calls on one context may be made from
+ * several host threads and on several streams.
+ */
+#ifndef PAPER_2402_09481_AMD_EXTRACTOR_H
+#define PAPER_2402_09481_AMD_EXTRACTOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------- */
+#define EXT_OK 0
+#define EXT_EINVAL (-1)      /* null pointer, size out of range, z overlapping x or y, bad flags */
+#define EXT_ENOTNA (-2)      /* length must be a prime with 2 as a primitive root */
+#define EXT_EDEGENERATE (-3) /* Dodis et al.: x is all zeros or all ones */
+#define EXT_ENOMEM (-4)      /* workspace does not fit the context's HBM budget */
+#define EXT_ETOOLARGE (-5)   /* the transform length would exceed 2^32 */
+#define EXT_EDEVICE (-6)     /* a HIP runtime call failed */
+
+/* ---- flags ---------------------------------------------------------- */
+/* Toeplitz seed order. PAPER (default): the matrix of eq. (toep) in the
+ * section "Toeplitz", entry (i, j) = y_{(i-j) mod (n+m-1)}. LINEAR:
+ * z_i = XOR_j s_{i-j+n-1} x_j. The two are one seed rotation apart:
+ * s_k = y_{(k+m) mod (n+m-1)}. */
+#define EXT_SEED_PAPER 0u
+#define EXT_SEED_LINEAR 1u
+/* Wait for the stream and return the device status. */
+#define EXT_SYNC 2u
+
+typedef struct ext_ctx ext_ctx;
+
+/* Create a context on HIP device `hip_device`: uploads the twiddle tables of
+ * both fields and sets up the workspace pool, capped at hbm_budget_bytes
+ * (0 = 90% of the device's free memory). tune_json: path of an autotune
+ * table written by the library's tuner, or NULL for built-in defaults.
+ * Returns EXT_OK and *out, or an error code and *out = NULL. */
+int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const char *tune_json);
+
+/* Synchronise the device, free all device memory of the context. NULL is a no-op. */
+void ext_destroy(ext_ctx *ctx);
+
+/* Toeplitz extractor (section "Toeplitz", eq. toeplitz-ext and eq. toep;
+ * embedding into a circulant, eq. toeplitz-embed and Alg. 2).
+ *   x: n bits (the weak input), y: n+m-1 bits (the seed), z: m bits.
+ *   Requires 1 <= m <= n. z_i = XOR_{j<n} toep(y)[i][j] x_j over GF(2).
+ *   flags: EXT_SEED_PAPER | EXT_SEED_LINEAR, optionally | EXT_SYNC. */
+int extract_toeplitz(ext_ctx *ctx, const uint64_t *x, uint64_t n, const uint64_t *y, uint64_t m,
+                     uint64_t *z, uint32_t flags, int32_t *status, void *stream);
+
+/* Circulant extractor (Definition of Circulant, eq. circ-matrix; computed by
+ * the Dodis et al. route on x' = [x, 0], section "Dodis (and Circulant)
+ * implementation").
+ *   x: n_in bits; n = n_in + 1 must be a prime with primitive root 2
+ *   (EXT_ENOTNA otherwise); y: n bits; z: m bits, 1 <= m <= n - 1.
+ *   z_i = XOR_{j<n} x'_{(j-i) mod n} y_j. */
+int extract_circulant(ext_ctx *ctx, const uint64_t *x, uint64_t n_in, const uint64_t *y, uint64_t m,
+                      uint64_t *z, uint32_t flags, int32_t *status, void *stream);
+
+/* Dodis et al. two-source extractor (section "Dodis et al.", eq. DodisOUT with
+ * cyclic-shift matrices; convolution form Dodis(x,y)_i = (R(x) * y)_i with
+ * indices mod n, Alg. 1).
+ *   x, y: n bits each; n prime with primitive root 2 (EXT_ENOTNA otherwise);
+ *   1 <= m <= n; x must be neither all zeros nor all ones (device check,
+ *   EXT_EDEGENERATE via status). z_i = XOR_{j<n} x_{(j-i) mod n} y_j. */
+int extract_dodis(ext_ctx *ctx, const uint64_t *x, const uint64_t *y, uint64_t n, uint64_t m, uint64_t *z,
+                  uint32_t flags, int32_t *status, void *stream);
+
+/* ---- batched entry point -------------------------------------------- */
+#define EXT_KIND_TOEPLITZ 0
+#define EXT_KIND_CIRCULANT 1
+#define EXT_KIND_DODIS 2
+
+typedef struct ext_job {
+    int32_t kind;          /* EXT_KIND_* */
+    uint32_t flags;        /* EXT_SEED_* (EXT_SYNC is ignored per job) */
+    uint64_t n;            /* input length as for the single calls (Circulant: n_in) */
+    uint64_t m;            /* output bits */
+    const uint64_t *x;     /* device */
+    const uint64_t *y;     /* device */
+    uint64_t *z;           /* device */
+    int32_t *status;       /* device or pinned, nullable: device-side status */
+    int32_t err;           /* out: host-side validation result for this job */
+    int32_t reserved;
+} ext_job;
+
+/* Run many independent extractions (the paper's many privacy-amplification
+ * blocks, section "Cryptomite for privacy amplification in QKD") as a few
+ * grouped launches: jobs are grouped by transform size; small sizes run one
+ * workgroup per job in a single launch, larger ones as batched multi-pass
+ * launches; the launch sequence for a batch signature is captured once into
+ * a HIP graph and replayed. `jobs` is a host array of `count` entries.
+ * Each job is validated on the host first and gets job.err; invalid jobs are
+ * skipped (their z untouched). Returns EXT_OK if every job was enqueued, the
+ * first failing job's code if some were skipped, or a context-level error
+ * (EXT_ENOMEM, EXT_EDEVICE) with nothing enqueued. flags: 0 or EXT_SYNC. */
+int extract_batch(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t flags, void *stream);
+
+/* The same jobs, one extraction call sequence per job (no grouping, no
+ * graph) — the comparison point for extract_batch. */
+int extract_batch_unbatched(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t flags, void *stream);
+
+/* ---- sizes, memory, utilities --------------------------------------- */
+
+/* Device workspace bytes one extraction of this shape takes from the pool
+ * (0 if the shape is invalid). kind: EXT_KIND_*; n as for the calls. */
+size_t ext_workspace_bytes(int32_t kind, uint64_t n, uint64_t m);
+
+/* Transform length L and field (32 or 64 = word bits) chosen for a shape; 0 on error. */
+uint64_t ext_plan_length(int32_t kind, uint64_t n, uint64_t m, int32_t *word_bits);
+
+/* Pool accounting: budget, bytes currently leased by in-flight calls, bytes
+ * held by the pool (leased + cached). Any pointer may be NULL. */
+int ext_mem_stats(ext_ctx *ctx, size_t *budget, size_t *in_use, size_t *reserved);
+
+/* Release cached (not leased) workspace back to the device. */
+int ext_trim(ext_ctx *ctx);
+
+/* Primes with 2 as a primitive root (footnote of the Circulant definition;
+ * utilities next_na_set / closest_na_set):
+ * ext_is_na_prime: 1 if n is prime and 2 generates (Z/nZ)*, else 0.
+ * ext_next_na: smallest such prime >= v (0 if beyond 2^63).
+ * ext_closest_na: the nearest one to v; the smaller on a tie. */
+int ext_is_na_prime(uint64_t n);
+uint64_t ext_next_na(uint64_t v);
+uint64_t ext_closest_na(uint64_t v);
+
+/* ---- tracing ----------------------------------------------------------
+ * With profiling on, every kernel launch an extraction call enqueues (not the
+ * graph-replayed batches) is bracketed by HIP events on the call's stream.
+ * ext_profile_read waits for those events and writes one line per launch,
+ * "<kernel label> <milliseconds>\n", into buf (NUL-terminated, truncated to
+ * cap), then forgets them. Returns the number of launches or a negative code. */
+int ext_profile(ext_ctx *ctx, int enable);
+int ext_profile_read(ext_ctx *ctx, char *buf, size_t cap);
+
+/* Static text for an EXT_E* code. */
+const char *ext_strerror(int code);
+
+/* Library version string. */
+const char *ext_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -91,22 +91,43 @@ static int parity_window_and(const uint64_t *a, uint64_t off, const uint64_t *v,
     return __builtin_parityll(acc);
 }
 
-/* reversed copy: r_k = a_{len-1-k}; one spare zero word at the end for window reads */
+/* bit order of one word reversed: bit b moves to bit 63 - b (swap halves, then
+ * quarters, ... down to single bits) */
+static uint64_t rev64(uint64_t v) {
+    v = (v >> 32) | (v << 32);
+    v = ((v >> 16) & 0x0000FFFF0000FFFFull) | ((v & 0x0000FFFF0000FFFFull) << 16);
+    v = ((v >> 8) & 0x00FF00FF00FF00FFull) | ((v & 0x00FF00FF00FF00FFull) << 8);
+    v = ((v >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((v & 0x0F0F0F0F0F0F0F0Full) << 4);
+    v = ((v >> 2) & 0x3333333333333333ull) | ((v & 0x3333333333333333ull) << 2);
+    v = ((v >> 1) & 0x5555555555555555ull) | ((v & 0x5555555555555555ull) << 1);
+    return v;
+}
+
+/* reversed copy: r_k = a_{len-1-k}; the input's bits beyond len must be zero.
+ * With W words and pad = 64W - len, the reversal of all 64W bits has word i equal
+ * to rev64(a[W-1-i]) and bit k + pad equal to a_{len-1-k}; shifting it down by pad
+ * bits gives r. One spare zero word at the end for window reads. */
 static uint64_t *reversed(const uint64_t *a, uint64_t len) {
-    uint64_t *r = (uint64_t *)calloc((len + 63) / 64 + 2, 8);
-    for (uint64_t k = 0; k < len; ++k)
-        if (bit(a, len - 1 - k)) r[k >> 6] |= (uint64_t)1 << (k & 63);
+    uint64_t W = (len + 63) / 64, pad = 64 * W - len;
+    uint64_t *full = (uint64_t *)calloc(W + 2, 8);
+    uint64_t *r = (uint64_t *)calloc(W + 2, 8);
+    for (uint64_t i = 0; i < W; ++i) full[i] = rev64(a[W - 1 - i]);
+    for (uint64_t i = 0; i < W; ++i)
+        r[i] = pad ? ((full[i] >> pad) | (full[i + 1] << (64 - pad))) : full[i];
+    free(full);
     return r;
 }
 
-/* two periods a || a of an len-bit string, plus a spare zero word */
+/* two periods a || a of an len-bit string (input bits beyond len zero): the second
+ * copy is a shifted up by len bits. A spare zero word at the end. */
 static uint64_t *doubled(const uint64_t *a, uint64_t len) {
+    uint64_t W = (len + 63) / 64, q = len >> 6, b = len & 63;
     uint64_t *d = (uint64_t *)calloc((2 * len + 63) / 64 + 2, 8);
-    for (uint64_t k = 0; k < len; ++k)
-        if (bit(a, k)) {
-            d[k >> 6] |= (uint64_t)1 << (k & 63);
-            d[(k + len) >> 6] |= (uint64_t)1 << ((k + len) & 63);
-        }
+    for (uint64_t i = 0; i < W; ++i) {
+        d[i] |= a[i];
+        d[q + i] |= a[i] << b;
+        if (b) d[q + i + 1] |= a[i] >> (64 - b);
+    }
     return d;
 }
 

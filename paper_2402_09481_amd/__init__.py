@@ -1,0 +1,198 @@
+"""MI355X (gfx950) convolution extractors: Toeplitz, Circulant, Dodis et al.
+
+Python binding of libextractor.so (``include/extractor.h``). It only
+marshals arguments: every step of an extraction runs in the library's HIP
+kernels. PyTorch is used for device memory and streams.
+
+Bit strings are packed little-endian uint64 words (bit i at
+``(w[i >> 6] >> (i & 63)) & 1``), held in torch int64/uint64 tensors on the GPU.
+The classes follow the paper's interface, ``Toeplitz(n_1, m).extract(x, y)``
+(section "Cryptomite for privacy amplification in QKD"), with
+``Circulant(n_1, m)`` taking the input length n_1 (n_1 + 1 must be a prime with
+2 as a primitive root) and ``Dodis(n, m)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import threading
+
+from . import _lib
+from ._lib import (EXT_EDEGENERATE, EXT_EINVAL, EXT_ENOMEM, EXT_ENOTNA, EXT_ETOOLARGE, EXT_OK,  # noqa: F401
+                   EXT_KIND_CIRCULANT, EXT_KIND_DODIS, EXT_KIND_TOEPLITZ, EXT_SEED_LINEAR, EXT_SEED_PAPER,
+                   EXT_SYNC, ExtError, ExtJob, KINDS)
+
+__all__ = ["Context", "Toeplitz", "Circulant", "Dodis", "extract", "extract_batch", "is_na_prime", "next_na_set",
+           "closest_na_set", "words", "ExtError", "ExtJob", "default_context"]
+
+
+def words(nbits: int) -> int:
+    return (int(nbits) + 63) >> 6
+
+
+def is_na_prime(n: int) -> bool:
+    return bool(_lib.load().ext_is_na_prime(int(n)))
+
+
+def next_na_set(v: int) -> int:
+    """Smallest prime >= v with 2 as a primitive root."""
+    return int(_lib.load().ext_next_na(int(v)))
+
+
+def closest_na_set(v: int) -> int:
+    """Prime with 2 as a primitive root nearest to v (the smaller on a tie)."""
+    return int(_lib.load().ext_closest_na(int(v)))
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a GPU tensor of packed uint64 words")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if t.element_size() != 8:
+        raise TypeError("packed words must be 64-bit (torch.int64 or torch.uint64)")
+    return t.data_ptr()
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Context:
+    """An extractor context on one device (twiddle tables, workspace pool)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, tune_json: str | None = None):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        rc = lib.ext_create(ctypes.byref(h), int(device), int(hbm_budget_bytes),
+                            tune_json.encode() if tune_json else None)
+        if rc != EXT_OK:
+            raise ExtError(rc, "ext_create")
+        self.handle = h
+        self.device = int(device)
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.ext_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mem_stats(self):
+        b, u, r = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        self._lib.ext_mem_stats(self.handle, ctypes.byref(b), ctypes.byref(u), ctypes.byref(r))
+        return {"budget": b.value, "in_use": u.value, "reserved": r.value}
+
+    def trim(self):
+        self._lib.ext_trim(self.handle)
+
+    def profile(self, enable: bool = True):
+        """Bracket every kernel launch of later extraction calls with HIP events."""
+        self._lib.ext_profile(self.handle, 1 if enable else 0)
+
+    def profile_read(self):
+        """[(kernel label, milliseconds)] for the launches traced since the last read."""
+        cap = 1 << 22
+        buf = ctypes.create_string_buffer(cap)
+        n = self._lib.ext_profile_read(self.handle, buf, cap)
+        if n < 0:
+            raise ExtError(n, "ext_profile_read")
+        out = []
+        for line in buf.value.decode().splitlines():
+            name, ms = line.rsplit(" ", 1)
+            out.append((name, float(ms)))
+        return out
+
+    # -- raw calls (device tensors in, device tensor out) --------------------------------
+    def extract(self, kind: str, x, y, n: int, m: int, z=None, seed_order: str = "paper", sync: bool = False,
+                status=None, stream=None, check: bool = True) -> "object":
+        import torch
+        if z is None:
+            z = torch.empty(words(m), dtype=torch.int64, device=x.device)
+        flags = (EXT_SEED_LINEAR if seed_order == "linear" else 0) | (EXT_SYNC if sync else 0)
+        st = ctypes.c_void_p(status.data_ptr()) if status is not None else None
+        s = _stream_handle(stream)
+        if kind == "toeplitz":
+            rc = self._lib.extract_toeplitz(self.handle, _ptr(x), int(n), _ptr(y), int(m), _ptr(z), flags, st, s)
+        elif kind == "circulant":
+            rc = self._lib.extract_circulant(self.handle, _ptr(x), int(n), _ptr(y), int(m), _ptr(z), flags, st, s)
+        elif kind == "dodis":
+            rc = self._lib.extract_dodis(self.handle, _ptr(x), _ptr(y), int(n), int(m), _ptr(z), flags, st, s)
+        else:
+            raise ValueError("unknown extractor kind %r" % kind)
+        if check and rc != EXT_OK:
+            raise ExtError(rc, "extract_" + kind)
+        return z if check else (rc, z)
+
+    def batch(self, jobs, sync: bool = False, stream=None, unbatched: bool = False):
+        """jobs: list of dicts with kind, n, m, x, y, z[, seed_order, status]. Returns the
+        library's return code and the per-job host validation codes."""
+        arr = (ExtJob * len(jobs))()
+        for i, j in enumerate(jobs):
+            arr[i].kind = KINDS[j["kind"]]
+            arr[i].flags = EXT_SEED_LINEAR if j.get("seed_order") == "linear" else 0
+            arr[i].n = int(j["n"])
+            arr[i].m = int(j["m"])
+            arr[i].x = _ptr(j["x"])
+            arr[i].y = _ptr(j["y"])
+            arr[i].z = _ptr(j["z"])
+            st = j.get("status")
+            arr[i].status = st.data_ptr() if st is not None else None
+        fn = self._lib.extract_batch_unbatched if unbatched else self._lib.extract_batch
+        rc = fn(self.handle, arr, len(jobs), EXT_SYNC if sync else 0, _stream_handle(stream))
+        return rc, [arr[i].err for i in range(len(jobs))]
+
+
+_default = {}
+_default_lock = threading.Lock()
+
+
+def default_context(device: int = 0) -> Context:
+    with _default_lock:
+        if device not in _default:
+            _default[device] = Context(device)
+        return _default[device]
+
+
+def extract(kind: str, x, y, n: int, m: int, **kw):
+    return default_context(x.device.index or 0).extract(kind, x, y, n, m, **kw)
+
+
+def extract_batch(jobs, **kw):
+    dev = jobs[0]["x"].device.index or 0 if jobs else 0
+    return default_context(dev).batch(jobs, **kw)
+
+
+class _Extractor:
+    kind = ""
+
+    def __init__(self, n: int, m: int, seed_order: str = "paper", context: Context | None = None):
+        self.n, self.m, self.seed_order, self.context = int(n), int(m), seed_order, context
+
+    def extract(self, x, y, z=None, stream=None, sync: bool = True):
+        ctx = self.context or default_context(x.device.index or 0)
+        return ctx.extract(self.kind, x, y, self.n, self.m, z=z, seed_order=self.seed_order, sync=sync,
+                           stream=stream)
+
+
+class Toeplitz(_Extractor):
+    """Toeplitz(n_1, m): x has n_1 bits, the seed n_1 + m - 1 bits."""
+    kind = "toeplitz"
+
+
+class Circulant(_Extractor):
+    """Circulant(n_1, m): x has n_1 bits, the seed n_1 + 1 bits (n_1 + 1 prime, primitive root 2)."""
+    kind = "circulant"
+
+
+class Dodis(_Extractor):
+    """Dodis(n, m): x and y have n bits (n prime with primitive root 2)."""
+    kind = "dodis"

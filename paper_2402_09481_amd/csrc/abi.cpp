@@ -1,0 +1,1032 @@
+// C-ABI of the extractor library: argument validation, planning, the
+// stream-ordered workspace pool, launch sequences, batching with HIP graphs,
+// and the prime utilities. See include/extractor.h for the contract.
+#include "../../include/extractor.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "field.h"
+#include "kernels.h"
+
+using namespace ext;
+
+namespace {
+
+// ------------------------------------------------------------------ primes with primitive root 2
+
+typedef unsigned __int128 u128;
+
+uint64_t mulmod64(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+uint64_t powmod64(uint64_t a, uint64_t e, uint64_t m) {
+    uint64_t r = 1 % m;
+    a %= m;
+    while (e) {
+        if (e & 1) r = mulmod64(r, a, m);
+        a = mulmod64(a, a, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Deterministic Miller-Rabin for 64-bit integers (the first 12 primes as bases suffice).
+bool is_prime64(uint64_t n) {
+    if (n < 2) return false;
+    static const uint64_t small[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    for (uint64_t p : small) {
+        if (n % p == 0) return n == p;
+    }
+    uint64_t d = n - 1;
+    int s = 0;
+    while (!(d & 1)) {
+        d >>= 1;
+        ++s;
+    }
+    for (uint64_t a : small) {
+        uint64_t x = powmod64(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int r = 1; r < s; ++r) {
+            x = mulmod64(x, x, n);
+            if (x == n - 1) {
+                comp = false;
+                break;
+            }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b) {
+    while (b) {
+        uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Pollard's rho (Brent's cycle detection) for a composite n.
+uint64_t rho(uint64_t n) {
+    if (n % 2 == 0) return 2;
+    for (uint64_t c = 1;; ++c) {
+        uint64_t y = 2, x = 2, g = 1, q = 1, ys = 2;
+        uint64_t r = 1;
+        const uint64_t mstep = 128;
+        auto f = [&](uint64_t v) { return (mulmod64(v, v, n) + c) % n; };
+        do {
+            x = y;
+            for (uint64_t i = 0; i < r; ++i) y = f(y);
+            uint64_t k = 0;
+            do {
+                ys = y;
+                for (uint64_t i = 0; i < std::min(mstep, r - k); ++i) {
+                    y = f(y);
+                    q = mulmod64(q, x > y ? x - y : y - x, n);
+                }
+                g = gcd64(q, n);
+                k += mstep;
+            } while (k < r && g == 1);
+            r <<= 1;
+        } while (g == 1);
+        if (g == n) {
+            do {
+                ys = f(ys);
+                g = gcd64(x > ys ? x - ys : ys - x, n);
+            } while (g == 1);
+        }
+        if (g != n) return g;
+    }
+}
+
+void factor_into(uint64_t n, std::vector<uint64_t> &out) {
+    if (n == 1) return;
+    for (uint64_t p = 2; p < 1000 && p * p <= n; ++p) {
+        if (n % p == 0) {
+            out.push_back(p);
+            while (n % p == 0) n /= p;
+        }
+    }
+    if (n == 1) return;
+    if (is_prime64(n)) {
+        out.push_back(n);
+        return;
+    }
+    uint64_t d = rho(n);
+    factor_into(d, out);
+    factor_into(n / d, out);
+}
+
+bool is_na(uint64_t n) {
+    if (n < 3 || !is_prime64(n)) return false;
+    std::vector<uint64_t> fs;
+    factor_into(n - 1, fs);
+    std::sort(fs.begin(), fs.end());
+    fs.erase(std::unique(fs.begin(), fs.end()), fs.end());
+    for (uint64_t q : fs)
+        if (powmod64(2, (n - 1) / q, n) == 1) return false;
+    return true;
+}
+
+// ------------------------------------------------------------------ fields on the host
+
+template <class F>
+std::vector<typename F::T> table_pow(typename F::T base, size_t count) {
+    std::vector<typename F::T> t(count);
+    typename F::T acc = 1;
+    for (size_t j = 0; j < count; ++j) {
+        t[j] = F::to_tw(acc);
+        acc = F::mulmod(acc, base);
+    }
+    return t;
+}
+
+int ceil_log2(uint64_t v) {
+    int l = 0;
+    while ((uint64_t(1) << l) < v) ++l;
+    return l;
+}
+
+// ------------------------------------------------------------------ plan
+
+struct Plan {
+    int field = FIELD_BB;
+    int lg = 0;
+    bool small = false;
+    int nlev = 0;
+    int lgr[4] = {0, 0, 0, 0};
+};
+
+constexpr int MIN_LEVEL_LG = 7;
+constexpr int MIN_LG = 6;
+
+// Level sizes: the last (contiguous) level takes up to its cap, strided levels
+// are balanced and kept at or below the preferred size (LDS tile <= 64 KiB).
+bool split_levels(int field, int lg, Plan &p) {
+    const int cap_c = max_contig_lg(field), cap_s = max_strided_lg(field);
+    const int pref_s = field == FIELD_BB ? 10 : cap_s;
+    for (int k = 2; k <= 4; ++k) {
+        if (lg < MIN_LEVEL_LG * k) return false;
+        if (lg > cap_c + (k - 1) * cap_s) continue;
+        int c = std::max(lg - (k - 1) * pref_s, (lg + k - 1) / k);
+        c = std::min(c, cap_c);
+        c = std::max(c, MIN_LEVEL_LG);
+        int rem = lg - c;
+        int ns = k - 1;
+        if (rem > ns * cap_s || rem < ns * MIN_LEVEL_LG) continue;
+        p.nlev = k;
+        for (int i = 0; i < ns; ++i) {
+            int share = rem / (ns - i) + ((rem % (ns - i)) ? 1 : 0);
+            share = std::min(share, cap_s);
+            p.lgr[i] = share;
+            rem -= share;
+        }
+        if (rem != 0) continue;
+        p.lgr[k - 1] = c;
+        return true;
+    }
+    return false;
+}
+
+// force: 0 = automatic, 1 = 15*2^27+1, 2 = Goldilocks (testing aid)
+int make_plan(uint64_t Lmin, int force, Plan &p) {
+    p = Plan();
+    p.lg = std::max(MIN_LG, ceil_log2(Lmin));
+    if (p.lg > 32) return EXT_ETOOLARGE;
+    p.field = p.lg <= FBB::LGMAX ? FIELD_BB : FIELD_GL;
+    if (force == 1) {
+        if (p.lg > FBB::LGMAX) return EXT_ETOOLARGE;
+        p.field = FIELD_BB;
+    } else if (force == 2) {
+        p.field = FIELD_GL;
+        p.lg = std::max(p.lg, 2 * MIN_LEVEL_LG);
+    }
+    if (p.field == FIELD_BB && p.lg <= max_small_lg()) {
+        p.small = true;
+        return EXT_OK;
+    }
+    return split_levels(p.field, p.lg, p) ? EXT_OK : EXT_ETOOLARGE;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t a = 0, b = 0, pb = 0, flags = 0, total = 0;
+};
+
+Layout workspace_layout(const Plan &p) {
+    Layout l;
+    if (p.small) return l;
+    const size_t L = size_t(1) << p.lg;
+    const size_t w = p.field == FIELD_BB ? 4 : 8;
+    l.a = 0;
+    l.b = align256(L * w);
+    l.pb = l.b + align256(L * w);
+    l.flags = l.pb + align256((L / 64 + 2) * 8);
+    l.total = l.flags + 256;
+    return l;
+}
+
+// ------------------------------------------------------------------ job description
+
+struct Shape {
+    int kind;
+    uint64_t n, m;     // as passed by the caller
+    uint64_t nfold;    // 0 or the circulant length
+    uint64_t Lmin;
+    uint64_t out_len;
+};
+
+int shape_of(int kind, uint64_t n, uint64_t m, Shape &s) {
+    s.kind = kind;
+    s.n = n;
+    s.m = m;
+    if (kind == EXT_KIND_TOEPLITZ) {
+        if (n < 1 || m < 1 || m > n) return EXT_EINVAL;
+        if (n > (uint64_t(1) << 40)) return EXT_ETOOLARGE;
+        s.nfold = 0;
+        s.Lmin = n + m - 1;
+        s.out_len = m;
+    } else if (kind == EXT_KIND_CIRCULANT) {
+        if (n < 1 || m < 1 || m > n) return EXT_EINVAL;
+        if (n > (uint64_t(1) << 40)) return EXT_ETOOLARGE;
+        s.nfold = n + 1;
+        s.Lmin = 2 * (n + 1) - 1;
+        s.out_len = m + n + 1;
+    } else if (kind == EXT_KIND_DODIS) {
+        if (n < 1 || m < 1 || m > n) return EXT_EINVAL;
+        if (n > (uint64_t(1) << 40)) return EXT_ETOOLARGE;
+        s.nfold = n;
+        s.Lmin = 2 * n - 1;
+        s.out_len = m + n;
+    } else {
+        return EXT_EINVAL;
+    }
+    if (s.Lmin > (uint64_t(1) << 32)) return EXT_ETOOLARGE;
+    return EXT_OK;
+}
+
+int check_primes(const Shape &s) {
+    if (s.kind == EXT_KIND_CIRCULANT && !is_na(s.n + 1)) return EXT_ENOTNA;
+    if (s.kind == EXT_KIND_DODIS && !is_na(s.n)) return EXT_ENOTNA;
+    return EXT_OK;
+}
+
+bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
+    uintptr_t x0 = (uintptr_t)a, x1 = x0 + abytes, y0 = (uintptr_t)b, y1 = y0 + bbytes;
+    return x0 < y1 && y0 < x1;
+}
+
+uint64_t words(uint64_t bits) { return (bits + 63) >> 6; }
+
+uint64_t seed_bits(const Shape &s) {
+    if (s.kind == EXT_KIND_TOEPLITZ) return s.n + s.m - 1;
+    if (s.kind == EXT_KIND_CIRCULANT) return s.n + 1;
+    return s.n;
+}
+
+int validate(const Shape &s, const uint64_t *x, const uint64_t *y, const uint64_t *z, uint32_t flags) {
+    if (!x || !y || !z) return EXT_EINVAL;
+    if (flags & ~(EXT_SEED_LINEAR | EXT_SYNC)) return EXT_EINVAL;
+    const size_t zb = words(s.m) * 8;
+    if (overlaps(z, zb, x, words(s.n) * 8) || overlaps(z, zb, y, words(seed_bits(s)) * 8)) return EXT_EINVAL;
+    return check_primes(s);
+}
+
+// Pointwise constant: BB folds L^-1 and two Montgomery factors, GL just L^-1.
+uint64_t pointwise_K(const Plan &p) {
+    if (p.field == FIELD_BB) {
+        uint32_t Linv = FBB::powmod(FBB::powmod(2, p.lg), FBB::P - 2);
+        uint32_t R = FBB::R_MOD_P;
+        return FBB::mulmod(FBB::mulmod(Linv, R), R);
+    }
+    return FGL::powmod(FGL::powmod(2, p.lg), FGL::P - 2);
+}
+
+JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint64_t *y, uint64_t *z, int32_t *status,
+                   uint32_t flags, char *ws) {
+    JobDev j;
+    std::memset(&j, 0, sizeof(j));
+    const Layout l = workspace_layout(p);
+    if (ws) {
+        j.A = ws + l.a;
+        j.B = ws + l.b;
+        j.pb = (uint64_t *)(ws + l.pb);
+        j.flags = (uint32_t *)(ws + l.flags);
+    }
+    j.z = z;
+    j.status = status;
+    j.L = uint64_t(1) << p.lg;
+    j.m = s.m;
+    j.nfold = s.nfold;
+    j.out_len = s.out_len;
+    j.K = pointwise_K(p);
+    if (s.kind == EXT_KIND_TOEPLITZ) {
+        const uint64_t N = s.n + s.m - 1;
+        j.ex = Emb{x, s.n, 0, 0, 0, EMB_PREFIX, 0};
+        const uint64_t rot = (flags & EXT_SEED_LINEAR) ? 0 : (s.m % N);
+        j.ey = Emb{y, N, s.n - 1, N, rot, EMB_SEED, 0};
+        j.degen_n = 0;
+    } else if (s.kind == EXT_KIND_CIRCULANT) {
+        const uint64_t n = s.n + 1;
+        j.ex = Emb{x, s.n, 0, n, 0, EMB_REVERSE, 0};
+        j.ey = Emb{y, n, 0, 0, 0, EMB_PREFIX, 0};
+        j.degen_n = 0;
+    } else {
+        j.ex = Emb{x, s.n, 0, s.n, 0, EMB_REVERSE, 0};
+        j.ey = Emb{y, s.n, 0, 0, 0, EMB_PREFIX, 0};
+        j.degen_n = s.n;
+    }
+    return j;
+}
+
+// ------------------------------------------------------------------ stream-ordered workspace pool
+
+struct Block {
+    char *ptr;
+    size_t size;
+    hipEvent_t ev;       // recorded after the last use
+    hipStream_t stream;  // stream of the last use
+    bool used;           // ev valid
+};
+
+}  // namespace
+
+struct ext_ctx {
+    int device = 0;
+    size_t budget = 0;
+    size_t reserved = 0;  // pool bytes (cached + leased) and tables
+    size_t leased = 0;
+    std::vector<Block> free_blocks;
+    std::mutex mu;
+    Tables tb[2];
+    void *tb_mem[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int force_field = 0;
+    hipStream_t capture_stream = nullptr;
+    // pinned status words for EXT_SYNC calls without a status pointer
+    std::vector<int32_t *> pinned_status;
+    // batch graph cache
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        JobDev *desc_dev = nullptr;
+        JobDev *desc_host = nullptr;  // pinned
+        size_t ndesc = 0;
+        hipEvent_t done = nullptr;
+        bool ever = false;
+    };
+    std::map<std::string, GraphEntry> graphs;
+    // tracing
+    bool profile = false;
+    struct Mark {
+        std::string label;
+        hipEvent_t a, b;
+    };
+    std::vector<Mark> marks;
+};
+
+namespace {
+
+struct Lease {
+    char *ptr = nullptr;
+    size_t size = 0;
+};
+
+// Take a block of at least `size` bytes usable on `stream`.
+int pool_acquire(ext_ctx *c, size_t size, hipStream_t stream, Lease &out) {
+    out = Lease();
+    if (size == 0) return EXT_OK;
+    size = align256(size);
+    std::lock_guard<std::mutex> g(c->mu);
+    int best = -1;
+    for (size_t i = 0; i < c->free_blocks.size(); ++i) {
+        Block &b = c->free_blocks[i];
+        if (b.size < size || b.size > 2 * size + (size_t(64) << 20)) continue;
+        if (b.used && b.stream != stream && hipEventQuery(b.ev) != hipSuccess) continue;
+        if (best < 0 || b.size < c->free_blocks[best].size) best = (int)i;
+    }
+    if (best < 0) {
+        // any idle block of a usable size, or room in the budget
+        if (c->reserved + size > c->budget) {
+            // release idle cached blocks until the new one fits
+            for (size_t i = 0; i < c->free_blocks.size() && c->reserved + size > c->budget;) {
+                Block &b = c->free_blocks[i];
+                if (!b.used || hipEventQuery(b.ev) == hipSuccess) {
+                    if (b.used) hipEventDestroy(b.ev);
+                    hipFree(b.ptr);
+                    c->reserved -= b.size;
+                    c->free_blocks.erase(c->free_blocks.begin() + i);
+                } else {
+                    ++i;
+                }
+            }
+            if (c->reserved + size > c->budget) return EXT_ENOMEM;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, size) != hipSuccess) {
+            (void)hipGetLastError();
+            return EXT_ENOMEM;
+        }
+        c->reserved += size;
+        c->leased += size;
+        out.ptr = (char *)p;
+        out.size = size;
+        return EXT_OK;
+    }
+    Block b = c->free_blocks[best];
+    c->free_blocks.erase(c->free_blocks.begin() + best);
+    if (b.used) {
+        if (b.stream != stream) hipStreamWaitEvent(stream, b.ev, 0);
+        hipEventDestroy(b.ev);
+    }
+    c->leased += b.size;
+    out.ptr = b.ptr;
+    out.size = b.size;
+    return EXT_OK;
+}
+
+void pool_release(ext_ctx *c, Lease &l, hipStream_t stream) {
+    if (!l.ptr) return;
+    Block b;
+    b.ptr = l.ptr;
+    b.size = l.size;
+    b.stream = stream;
+    b.used = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) == hipSuccess;
+    if (b.used) hipEventRecord(b.ev, stream);
+    std::lock_guard<std::mutex> g(c->mu);
+    c->leased -= l.size;
+    c->free_blocks.push_back(b);
+    l = Lease();
+}
+
+// ------------------------------------------------------------------ launch sequences
+
+// Brackets one launch with timing events when tracing is on.
+struct Tracer {
+    ext_ctx *c;
+    hipStream_t s;
+    bool on;
+    hipEvent_t a = nullptr;
+    Tracer(ext_ctx *c_, hipStream_t s_, bool capturing) : c(c_), s(s_), on(c_->profile && !capturing) {}
+    void begin() {
+        if (!on) return;
+        if (hipEventCreate(&a) != hipSuccess) {
+            a = nullptr;
+            return;
+        }
+        hipEventRecord(a, s);
+    }
+    void end(const std::string &label) {
+        if (!on || !a) return;
+        hipEvent_t b = nullptr;
+        if (hipEventCreate(&b) != hipSuccess) return;
+        hipEventRecord(b, s);
+        std::lock_guard<std::mutex> g(c->mu);
+        c->marks.push_back(ext_ctx::Mark{label, a, b});
+        a = nullptr;
+    }
+};
+
+// "<kind>[<word>,lgr=<log2 transform size>,mode=<pass mode>,arr=<0: input, 1: seed>]"
+std::string pass_label(const char *what, int field, int lgr, int mode, int which = 0) {
+    char b[112];
+    snprintf(b, sizeof b, "%s[%s,lgr=%d,mode=%d,arr=%d]", what, field == FIELD_BB ? "u32" : "u64", lgr, mode,
+             which);
+    return b;
+}
+
+// Enqueue the whole extraction for njobs jobs sharing one plan. jobs_dev: device
+// descriptors (batched launches) or nullptr with `one` for a single job.
+hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs_dev, const JobDev *one,
+                   uint64_t max_m, bool any_degen, hipStream_t s, bool capturing = false) {
+    const Tables &tb = c->tb[p.field];
+    Tracer tr(c, s, capturing);
+    if (p.small) {
+        tr.begin();
+        hipError_t e = launch_small(p.lg, njobs, jobs_dev, one, tb, s);
+        tr.end(pass_label("small", p.field, p.lg, 0));
+        return e;
+    }
+    const uint64_t L = uint64_t(1) << p.lg;
+    hipError_t e;
+    for (int which = 0; which < 2; ++which) {
+        uint64_t Mprev = L;
+        for (int i = 0; i + 1 < p.nlev; ++i) {
+            const Geometry g = strided_geometry(p.field, p.lgr[i]);
+            PassLaunch pl;
+            pl.field = p.field;
+            pl.lgr = p.lgr[i];
+            pl.mode = i == 0 ? S_FWD_BITS : S_FWD;
+            pl.which = which;
+            pl.Mprev = Mprev;
+            pl.S = Mprev >> p.lgr[i];
+            pl.tiles = (L / Mprev) * (pl.S / g.C);
+            pl.njobs = njobs;
+            pl.jobs = jobs_dev;
+            pl.one = one;
+            tr.begin();
+            e = launch_strided(pl, tb, s);
+            tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, which));
+            if (e != hipSuccess) return e;
+            Mprev = pl.S;
+        }
+        const int lc = p.lgr[p.nlev - 1];
+        const Geometry g = contig_geometry(p.field, lc);
+        PassLaunch pl;
+        pl.field = p.field;
+        pl.lgr = lc;
+        pl.mode = which == 0 ? C_FWD : C_FUSED;
+        pl.which = which;
+        pl.S = 0;
+        pl.Mprev = 0;
+        pl.tiles = L >> lc;
+        pl.tiles /= (uint64_t)g.C;
+        pl.njobs = njobs;
+        pl.jobs = jobs_dev;
+        pl.one = one;
+        tr.begin();
+        e = launch_contig(pl, tb, s);
+        tr.end(pass_label("contig", p.field, pl.lgr, pl.mode, which));
+        if (e != hipSuccess) return e;
+    }
+    // inverse: strided levels backwards; level 0 writes packed parity
+    std::vector<uint64_t> mp(p.nlev);
+    uint64_t M = L;
+    for (int i = 0; i < p.nlev; ++i) {
+        mp[i] = M;
+        M >>= p.lgr[i];
+    }
+    for (int i = p.nlev - 2; i >= 0; --i) {
+        const Geometry g = strided_geometry(p.field, p.lgr[i]);
+        PassLaunch pl;
+        pl.field = p.field;
+        pl.lgr = p.lgr[i];
+        pl.mode = i == 0 ? S_INV_PARITY : S_INV;
+        pl.which = 1;
+        pl.Mprev = mp[i];
+        pl.S = mp[i] >> p.lgr[i];
+        pl.tiles = (L / mp[i]) * (pl.S / g.C);
+        pl.njobs = njobs;
+        pl.jobs = jobs_dev;
+        pl.one = one;
+        tr.begin();
+        e = launch_strided(pl, tb, s);
+        tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, 1));
+        if (e != hipSuccess) return e;
+    }
+    if (any_degen && (e = launch_degen(njobs, jobs_dev, one, s)) != hipSuccess) return e;
+    tr.begin();
+    e = launch_pack(njobs, words(max_m), jobs_dev, one, s);
+    tr.end("pack");
+    return e;
+}
+
+int32_t *take_pinned_status(ext_ctx *c) {
+    std::lock_guard<std::mutex> g(c->mu);
+    if (!c->pinned_status.empty()) {
+        int32_t *p = c->pinned_status.back();
+        c->pinned_status.pop_back();
+        return p;
+    }
+    int32_t *p = nullptr;
+    if (hipHostMalloc((void **)&p, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+}
+
+void give_pinned_status(ext_ctx *c, int32_t *p) {
+    std::lock_guard<std::mutex> g(c->mu);
+    c->pinned_status.push_back(p);
+}
+
+int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint64_t *y, uint64_t m, uint64_t *z,
+                uint32_t flags, int32_t *status, hipStream_t s) {
+    if (!c) return EXT_EINVAL;
+    Shape sh;
+    int rc = shape_of(kind, n, m, sh);
+    if (rc) return rc;
+    if ((rc = validate(sh, x, y, z, flags)) != EXT_OK) return rc;
+    Plan p;
+    if ((rc = make_plan(sh.Lmin, c->force_field, p)) != EXT_OK) return rc;
+    if (hipSetDevice(c->device) != hipSuccess) return EXT_EDEVICE;
+    const Layout lay = workspace_layout(p);
+    Lease lease;
+    if ((rc = pool_acquire(c, lay.total, s, lease)) != EXT_OK) return rc;
+    int32_t *st = status;
+    int32_t *mine = nullptr;
+    if ((flags & EXT_SYNC) && !st) {
+        mine = take_pinned_status(c);
+        if (!mine) {
+            pool_release(c, lease, s);
+            return EXT_EDEVICE;
+        }
+        *mine = 0;
+        st = mine;
+    }
+    JobDev jd = make_jobdev(sh, p, x, y, z, st, flags, lease.ptr);
+    hipError_t e = enqueue(c, p, 1, nullptr, &jd, sh.m, jd.degen_n != 0, s);
+    pool_release(c, lease, s);
+    if (e != hipSuccess) {
+        if (mine) give_pinned_status(c, mine);
+        return EXT_EDEVICE;
+    }
+    if (flags & EXT_SYNC) {
+        if (hipStreamSynchronize(s) != hipSuccess) rc = EXT_EDEVICE;
+        else {
+            int32_t v = 0;
+            if (mine) v = *mine;
+            else if (hipMemcpy(&v, st, sizeof(v), hipMemcpyDefault) != hipSuccess) v = EXT_EDEVICE;
+            rc = v;
+        }
+        if (mine) give_pinned_status(c, mine);
+    }
+    return rc;
+}
+
+}  // namespace
+
+// ================================================================== C-ABI
+
+extern "C" {
+
+const char *ext_version(void) { return "paper_2402_09481_amd 0.1 (gfx950)"; }
+
+const char *ext_strerror(int code) {
+    switch (code) {
+        case EXT_OK: return "ok";
+        case EXT_EINVAL: return "invalid argument (null pointer, size out of range, overlapping output, bad flags)";
+        case EXT_ENOTNA: return "length must be a prime with 2 as a primitive root";
+        case EXT_EDEGENERATE: return "Dodis et al.: the input is all zeros or all ones";
+        case EXT_ENOMEM: return "workspace exceeds the context's HBM budget";
+        case EXT_ETOOLARGE: return "transform length would exceed 2^32";
+        case EXT_EDEVICE: return "HIP runtime error";
+    }
+    return "unknown error code";
+}
+
+int ext_is_na_prime(uint64_t n) { return is_na(n) ? 1 : 0; }
+
+uint64_t ext_next_na(uint64_t v) {
+    for (uint64_t c = std::max<uint64_t>(v, 3); c < (uint64_t(1) << 63); ++c)
+        if (is_na(c)) return c;
+    return 0;
+}
+
+uint64_t ext_closest_na(uint64_t v) {
+    uint64_t up = ext_next_na(v);
+    uint64_t lo = 0;
+    for (uint64_t c = v; c >= 3; --c)
+        if (is_na(c)) {
+            lo = c;
+            break;
+        }
+    if (lo == 0) return up;
+    if (up == 0) return lo;
+    return (v - lo) <= (up - v) ? lo : up;
+}
+
+size_t ext_workspace_bytes(int32_t kind, uint64_t n, uint64_t m) {
+    Shape s;
+    Plan p;
+    if (shape_of(kind, n, m, s) != EXT_OK) return 0;
+    if (make_plan(s.Lmin, 0, p) != EXT_OK) return 0;
+    return workspace_layout(p).total;
+}
+
+uint64_t ext_plan_length(int32_t kind, uint64_t n, uint64_t m, int32_t *word_bits) {
+    Shape s;
+    Plan p;
+    if (shape_of(kind, n, m, s) != EXT_OK) return 0;
+    if (make_plan(s.Lmin, 0, p) != EXT_OK) return 0;
+    if (word_bits) *word_bits = p.field == FIELD_BB ? 32 : 64;
+    return uint64_t(1) << p.lg;
+}
+
+int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const char *tune_json) {
+    (void)tune_json;
+    if (!out) return EXT_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return EXT_EDEVICE;
+    if (hipSetDevice(hip_device) != hipSuccess) return EXT_EDEVICE;
+    ext_ctx *c = new ext_ctx();
+    c->device = hip_device;
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
+        delete c;
+        return EXT_EDEVICE;
+    }
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)freeb);
+    const char *ff = getenv("EXT_FORCE_FIELD");  // testing aid: "bb" or "gl"
+    if (ff && !strcmp(ff, "gl")) c->force_field = 2;
+    if (ff && !strcmp(ff, "bb")) c->force_field = 1;
+    // twiddle tables
+    auto upload = [&](int f, int k, const void *src, size_t bytes) -> bool {
+        void *d = nullptr;
+        if (hipMalloc(&d, bytes) != hipSuccess) return false;
+        if (hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return false;
+        c->tb_mem[f][k] = d;
+        c->reserved += bytes;
+        return true;
+    };
+    bool ok = true;
+    {
+        using F = FBB;
+        auto lo = table_pow<F>(F::WMAX, size_t(1) << 16);
+        auto hi = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << 16), size_t(1) << (F::LGMAX - 16));
+        auto in = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << (F::LGMAX - TWIN_LG)), size_t(1) << TWIN_LG);
+        ok = ok && upload(FIELD_BB, 0, lo.data(), lo.size() * 4) && upload(FIELD_BB, 1, hi.data(), hi.size() * 4) &&
+             upload(FIELD_BB, 2, in.data(), in.size() * 4);
+    }
+    {
+        using F = FGL;
+        auto lo = table_pow<F>(F::WMAX, size_t(1) << 16);
+        auto hi = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << 16), size_t(1) << (F::LGMAX - 16));
+        auto in = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << (F::LGMAX - TWIN_LG)), size_t(1) << TWIN_LG);
+        ok = ok && upload(FIELD_GL, 0, lo.data(), lo.size() * 8) && upload(FIELD_GL, 1, hi.data(), hi.size() * 8) &&
+             upload(FIELD_GL, 2, in.data(), in.size() * 8);
+    }
+    if (ok) ok = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        ext_destroy(c);
+        return EXT_EDEVICE;
+    }
+    for (int f = 0; f < 2; ++f) c->tb[f] = Tables{c->tb_mem[f][0], c->tb_mem[f][1], c->tb_mem[f][2]};
+    *out = c;
+    return EXT_OK;
+}
+
+void ext_destroy(ext_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (auto &b : c->free_blocks) {
+        if (b.used) hipEventDestroy(b.ev);
+        hipFree(b.ptr);
+    }
+    for (auto &kv : c->graphs) {
+        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.desc_dev) hipFree(kv.second.desc_dev);
+        if (kv.second.desc_host) hipHostFree(kv.second.desc_host);
+        if (kv.second.done) hipEventDestroy(kv.second.done);
+    }
+    for (int f = 0; f < 2; ++f)
+        for (int k = 0; k < 3; ++k)
+            if (c->tb_mem[f][k]) hipFree(c->tb_mem[f][k]);
+    for (auto p : c->pinned_status) hipHostFree(p);
+    for (auto &mk : c->marks) {
+        hipEventDestroy(mk.a);
+        hipEventDestroy(mk.b);
+    }
+    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
+    delete c;
+}
+
+int ext_mem_stats(ext_ctx *c, size_t *budget, size_t *in_use, size_t *reserved) {
+    if (!c) return EXT_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (budget) *budget = c->budget;
+    if (in_use) *in_use = c->leased;
+    if (reserved) *reserved = c->reserved;
+    return EXT_OK;
+}
+
+int ext_trim(ext_ctx *c) {
+    if (!c) return EXT_EINVAL;
+    hipSetDevice(c->device);
+    std::lock_guard<std::mutex> g(c->mu);
+    for (size_t i = 0; i < c->free_blocks.size();) {
+        Block &b = c->free_blocks[i];
+        if (!b.used || hipEventQuery(b.ev) == hipSuccess) {
+            if (b.used) hipEventDestroy(b.ev);
+            hipFree(b.ptr);
+            c->reserved -= b.size;
+            c->free_blocks.erase(c->free_blocks.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+    return EXT_OK;
+}
+
+int extract_toeplitz(ext_ctx *ctx, const uint64_t *x, uint64_t n, const uint64_t *y, uint64_t m, uint64_t *z,
+                     uint32_t flags, int32_t *status, void *stream) {
+    return extract_one(ctx, EXT_KIND_TOEPLITZ, x, n, y, m, z, flags, status, (hipStream_t)stream);
+}
+
+int extract_circulant(ext_ctx *ctx, const uint64_t *x, uint64_t n_in, const uint64_t *y, uint64_t m, uint64_t *z,
+                      uint32_t flags, int32_t *status, void *stream) {
+    if (flags & EXT_SEED_LINEAR) return EXT_EINVAL;
+    return extract_one(ctx, EXT_KIND_CIRCULANT, x, n_in, y, m, z, flags, status, (hipStream_t)stream);
+}
+
+int extract_dodis(ext_ctx *ctx, const uint64_t *x, const uint64_t *y, uint64_t n, uint64_t m, uint64_t *z,
+                  uint32_t flags, int32_t *status, void *stream) {
+    if (flags & EXT_SEED_LINEAR) return EXT_EINVAL;
+    return extract_one(ctx, EXT_KIND_DODIS, x, n, y, m, z, flags, status, (hipStream_t)stream);
+}
+
+int extract_batch_unbatched(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t flags, void *stream) {
+    if (!ctx || (!jobs && count)) return EXT_EINVAL;
+    int first = EXT_OK;
+    for (size_t i = 0; i < count; ++i) {
+        ext_job &j = jobs[i];
+        j.err = extract_one(ctx, j.kind, j.x, j.n, j.y, j.m, j.z, j.flags & EXT_SEED_LINEAR, j.status,
+                            (hipStream_t)stream);
+        if (j.err && first == EXT_OK) first = j.err;
+    }
+    if ((flags & EXT_SYNC) && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return EXT_EDEVICE;
+    return first;
+}
+
+int extract_batch(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t flags, void *stream);
+
+int ext_profile(ext_ctx *c, int enable) {
+    if (!c) return EXT_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    c->profile = enable != 0;
+    return EXT_OK;
+}
+
+int ext_profile_read(ext_ctx *c, char *buf, size_t cap) {
+    if (!c) return EXT_EINVAL;
+    std::vector<ext_ctx::Mark> marks;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        marks.swap(c->marks);
+    }
+    std::string out;
+    int n = 0;
+    int rc = EXT_OK;
+    for (auto &mk : marks) {
+        float ms = 0.f;
+        if (hipEventSynchronize(mk.b) != hipSuccess || hipEventElapsedTime(&ms, mk.a, mk.b) != hipSuccess) rc = EXT_EDEVICE;
+        char line[160];
+        snprintf(line, sizeof line, "%s %.6f\n", mk.label.c_str(), ms);
+        out += line;
+        hipEventDestroy(mk.a);
+        hipEventDestroy(mk.b);
+        ++n;
+    }
+    if (buf && cap) {
+        size_t k = std::min(cap - 1, out.size());
+        memcpy(buf, out.data(), k);
+        buf[k] = 0;
+    }
+    return rc == EXT_OK ? n : rc;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batching
+
+namespace {
+
+struct Member {
+    size_t job;
+    Shape shape;
+    Plan plan;
+};
+
+std::string plan_key(const Plan &p) {
+    char b[64];
+    snprintf(b, sizeof b, "%d:%d:%d:%d.%d.%d.%d", p.field, p.lg, p.small ? 1 : 0, p.lgr[0], p.lgr[1], p.lgr[2],
+             p.lgr[3]);
+    return b;
+}
+
+}  // namespace
+
+extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t flags, void *stream_) {
+    if (!c || (!jobs && count)) return EXT_EINVAL;
+    if (flags & ~EXT_SYNC) return EXT_EINVAL;
+    hipStream_t stream = (hipStream_t)stream_;
+    if (hipSetDevice(c->device) != hipSuccess) return EXT_EDEVICE;
+    int first = EXT_OK;
+    // validate, plan, group
+    std::map<std::string, std::vector<Member>> groups;
+    for (size_t i = 0; i < count; ++i) {
+        ext_job &j = jobs[i];
+        Member mb;
+        mb.job = i;
+        int rc = shape_of(j.kind, j.n, j.m, mb.shape);
+        if (rc == EXT_OK && (j.flags & ~(EXT_SEED_LINEAR | EXT_SYNC))) rc = EXT_EINVAL;
+        if (rc == EXT_OK && j.kind != EXT_KIND_TOEPLITZ && (j.flags & EXT_SEED_LINEAR)) rc = EXT_EINVAL;
+        if (rc == EXT_OK) rc = validate(mb.shape, j.x, j.y, j.z, j.flags & EXT_SEED_LINEAR);
+        if (rc == EXT_OK) rc = make_plan(mb.shape.Lmin, c->force_field, mb.plan);
+        j.err = rc;
+        if (rc != EXT_OK) {
+            if (first == EXT_OK) first = rc;
+            continue;
+        }
+        groups[plan_key(mb.plan)].push_back(mb);
+    }
+    if (groups.empty()) return first;
+    // Chunks: groups are split so that one chunk's workspace stays under a cap;
+    // chunks run one after another and share one workspace lease.
+    const size_t cap = std::max<size_t>(size_t(1) << 30, std::min<size_t>(c->budget / 4, size_t(16) << 30));
+    struct Chunk {
+        Plan plan;
+        size_t first_desc, n;
+        uint64_t max_m;
+        bool any_degen;
+        size_t ws_each;
+    };
+    std::vector<Chunk> chunks;
+    std::vector<const Member *> order;
+    size_t max_ws = 0;
+    std::string sig;
+    for (auto &kv : groups) {
+        const Plan &p = kv.second.front().plan;
+        const size_t each = workspace_layout(p).total;
+        size_t per_chunk = each ? std::max<size_t>(1, cap / each) : kv.second.size();
+        per_chunk = std::min<size_t>(per_chunk, 65535);
+        for (size_t s0 = 0; s0 < kv.second.size(); s0 += per_chunk) {
+            Chunk ch;
+            ch.plan = p;
+            ch.first_desc = order.size();
+            ch.n = std::min(per_chunk, kv.second.size() - s0);
+            ch.max_m = 0;
+            ch.any_degen = false;
+            ch.ws_each = each;
+            for (size_t k = 0; k < ch.n; ++k) {
+                const Member &mb = kv.second[s0 + k];
+                order.push_back(&mb);
+                ch.max_m = std::max(ch.max_m, mb.shape.m);
+                ch.any_degen |= mb.shape.kind == EXT_KIND_DODIS;
+            }
+            max_ws = std::max(max_ws, each * ch.n);
+            chunks.push_back(ch);
+            char b[96];
+            snprintf(b, sizeof b, "%s#%zu:%llu:%d|", kv.first.c_str(), ch.n, (unsigned long long)ch.max_m,
+                     ch.any_degen ? 1 : 0);
+            sig += b;
+        }
+    }
+    Lease lease;
+    int rc = pool_acquire(c, max_ws, stream, lease);
+    if (rc != EXT_OK) return rc;
+    // graph cache entry for this batch signature
+    ext_ctx::GraphEntry *ge;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        ge = &c->graphs[sig];
+    }
+    if (!ge->desc_dev) {
+        ge->ndesc = order.size();
+        if (hipMalloc((void **)&ge->desc_dev, ge->ndesc * sizeof(JobDev)) != hipSuccess ||
+            hipHostMalloc((void **)&ge->desc_host, ge->ndesc * sizeof(JobDev), hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&ge->done, hipEventDisableTiming) != hipSuccess) {
+            pool_release(c, lease, stream);
+            return EXT_EDEVICE;
+        }
+    }
+    // the pinned descriptor staging of this signature may still be read by the previous replay's copy
+    if (ge->ever) hipEventSynchronize(ge->done);
+    for (auto &ch : chunks) {
+        for (size_t k = 0; k < ch.n; ++k) {
+            const Member &mb = *order[ch.first_desc + k];
+            const ext_job &j = jobs[mb.job];
+            char *ws = ch.ws_each ? lease.ptr + k * ch.ws_each : nullptr;
+            ge->desc_host[ch.first_desc + k] =
+                make_jobdev(mb.shape, mb.plan, j.x, j.y, j.z, j.status, j.flags & EXT_SEED_LINEAR, ws);
+        }
+    }
+    if (hipMemcpyAsync(ge->desc_dev, ge->desc_host, ge->ndesc * sizeof(JobDev), hipMemcpyHostToDevice, stream) !=
+        hipSuccess) {
+        pool_release(c, lease, stream);
+        return EXT_EDEVICE;
+    }
+    if (!ge->exec) {
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+        for (auto &ch : chunks) {
+            if (e != hipSuccess) break;
+            e = enqueue(c, ch.plan, (uint32_t)ch.n, ge->desc_dev + ch.first_desc, nullptr, ch.max_m, ch.any_degen,
+                        c->capture_stream, true);
+        }
+        hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ge->exec, graph, nullptr, nullptr, 0);
+        if (graph) hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            ge->exec = nullptr;
+            pool_release(c, lease, stream);
+            return EXT_EDEVICE;
+        }
+    }
+    hipError_t e = hipGraphLaunch(ge->exec, stream);
+    hipEventRecord(ge->done, stream);
+    ge->ever = true;
+    pool_release(c, lease, stream);
+    if (e != hipSuccess) return EXT_EDEVICE;
+    if ((flags & EXT_SYNC) && hipStreamSynchronize(stream) != hipSuccess) return EXT_EDEVICE;
+    return first;
+}

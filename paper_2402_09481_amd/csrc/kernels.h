@@ -1,0 +1,97 @@
+// Device-side job descriptors and the host-side launch interface of the
+// transform kernels. Shared by the kernel translation unit (ntt.hip) and the
+// C-ABI / planner (abi.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ext {
+
+// Embedding of a packed bit string into coefficient vector position i of a
+// length-L cyclic convolution (Alg. 1 and Alg. 2 embeddings, written as index maps):
+//   PREFIX  (Toeplitz input x, Dodis/Circulant seed y): i < len ? b_i : 0
+//   SEED    (Toeplitz seed): k = (i + a) mod L; k < N ? b_{(k + rot) mod N} : 0.
+//           With a = n - 1 this places s_k at (k - n + 1) mod L (linear order,
+//           rot = 0); rot = m gives the paper's order of eq. toep, for which the
+//           placement is Alg. 2's: v'[i] = y_i (i < m), v'[L-n+1+t] = y_{m+t}.
+//   REVERSE (Dodis/Circulant input): i < N ? b'_{(N - i) mod N} : 0, where
+//           b'_j = (j < len ? b_j : 0) — the reversal R(x) of the Dodis
+//           convolution form, on x' = [x, 0] for Circulant (len = N - 1).
+enum EmbMode : uint32_t { EMB_PREFIX = 0, EMB_SEED = 1, EMB_REVERSE = 2 };
+
+struct Emb {
+    const uint64_t *bits;
+    uint64_t len;
+    uint64_t a;
+    uint64_t N;
+    uint64_t rot;
+    uint32_t mode;
+    uint32_t pad_;
+};
+
+// One extraction as the kernels see it.
+struct JobDev {
+    void *A;           // L words: the input transform, then its spectrum
+    void *B;           // L words: the seed transform, then the product, then the convolution
+    uint64_t *pb;      // packed parity of coefficients [0, out_len) (+1 spare word)
+    uint32_t *flags;   // degenerate check: flags[0] = any one bit, flags[1] = any zero bit
+    uint64_t *z;       // caller's output, ceil(m/64) words
+    int32_t *status;   // caller's status word or nullptr
+    Emb ex, ey;        // embeddings of the input (into A) and the seed (into B)
+    uint64_t L;        // transform length
+    uint64_t m;        // output bits
+    uint64_t nfold;    // 0 (Toeplitz) or n (Dodis/Circulant: z_i = c_i ^ c_{i+n})
+    uint64_t out_len;  // coefficients whose parity is needed: m or m + n
+    uint64_t degen_n;  // bits of x checked for all-0/all-1 (Dodis), 0 = no check
+    uint64_t K;        // pointwise constant: folds L^-1 (and Montgomery factors)
+};
+
+struct Tables {
+    const void *lo;  // w_max^j, j < 2^16 (twiddle form)
+    const void *hi;  // w_max^(j 2^16), j < 2^(LGMAX-16)
+    const void *in;  // w_{2^14}^j, j < 2^14
+};
+
+constexpr int TWIN_LG = 14;
+
+// Field selector for the launchers.
+enum FieldId : int { FIELD_BB = 0, FIELD_GL = 1 };
+
+// Tile geometry (host copy of the kernels' compile-time choices).
+struct Geometry {
+    int C;   // columns (strided) or rows (contiguous) per workgroup
+    int NT;  // threads per workgroup
+};
+Geometry strided_geometry(int field, int lgr);
+Geometry contig_geometry(int field, int lgr);
+int max_strided_lg(int field);
+int max_contig_lg(int field);
+int max_small_lg();
+
+// Strided pass over columns: the array viewed as (L / Mprev) blocks of R x S
+// (row-major, R = 2^lgr rows at stride S), each column transformed.
+enum StridedMode : int { S_FWD_BITS = 0, S_FWD = 1, S_INV = 2, S_INV_PARITY = 3 };
+// Contiguous pass over rows of R = 2^lgr consecutive words (last level).
+enum ContigMode : int { C_FWD = 0, C_FUSED = 1 };
+
+struct PassLaunch {
+    int field, lgr, mode;
+    int which;            // 0: array A, 1: array B (ignored by C_FUSED, which reads A and B)
+    uint64_t S, Mprev;    // strided only
+    uint64_t tiles;       // workgroups per job
+    uint32_t njobs;
+    const JobDev *jobs;   // device array of njobs, or nullptr to use `one`
+    const JobDev *one;    // host copy for single-job launches (passed by value)
+};
+
+hipError_t launch_strided(const PassLaunch &p, const Tables &t, hipStream_t s);
+hipError_t launch_contig(const PassLaunch &p, const Tables &t, hipStream_t s);
+// Whole extraction in one workgroup (field FBB, L = 2^lg <= 2^14).
+hipError_t launch_small(int lg, uint32_t njobs, const JobDev *jobs, const JobDev *one, const Tables &t,
+                        hipStream_t s);
+// Packed parity -> z (fold, mask, degenerate check result, status).
+hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, const JobDev *one, hipStream_t s);
+// Dodis degenerate-input check (writes flags).
+hipError_t launch_degen(uint32_t njobs, const JobDev *jobs, const JobDev *one, hipStream_t s);
+
+}  // namespace ext

@@ -1,0 +1,732 @@
+// Transform kernels for the convolution extractors.
+//
+// The extractor output is the mod-2 reduction of an exact integer cyclic
+// convolution of two 0/1 vectors (Alg. 1 / Alg. 2), computed with the
+// convolution theorem: NTT(u * v) = NTT(u) . NTT(v) (section "The
+// number-theoretic transform and the convolution theorem").
+//
+// A transform of length L = R_1 R_2 ... R_k is done in k passes (the
+// "four-step" factorisation applied recursively). Pass i transforms, for each
+// block of size M_{i-1} = R_i ... R_k, the columns of that block viewed as an
+// R_i x M_i row-major matrix, then multiplies entry (row k_i, column c) by
+// w_{M_{i-1}}^(c k_i). The spectrum ends up in digit-reversed order, which is
+// harmless: the pointwise product is order-agnostic, and the inverse runs the
+// passes backwards (twiddles w^-(c k_i) applied before each column
+// transform), returning the convolution in natural order.
+//
+// Inside a pass each column (or row) of length R = 2^lgr is transformed by
+// radix-16 Stockham steps (the first forward step takes the leftover radix
+// 2, 4 or 8), exchanging data through LDS between steps. Step with radix r
+// and span Ns: group j reads elements j + t R/r (t < r), multiplies element
+// t by w_{Ns r}^(t (j mod Ns)), does an r-point DFT in registers and writes
+// output t to ((j - j mod Ns) r + j mod Ns) + t Ns. The output is in natural
+// order. The last step's output positions are the first step's input
+// positions of the same radix, so consecutive steps of opposite direction
+// can hand data over in registers.
+//
+// Passes:
+//   strided    S_FWD_BITS: embed packed bits (first pass of a forward transform)
+//              S_FWD: column transform, then twiddle, in place
+//              S_INV: twiddle^-1, then inverse column transform, in place
+//              S_INV_PARITY: as S_INV, then canonical residue mod 2, packed
+//   contiguous C_FWD: row transform (last level of the input's transform)
+//              C_FUSED: seed row transform, times the input's spectrum times
+//              L^-1, inverse row transform (last forward level of the seed,
+//              the pointwise product, first inverse level)
+//   small      whole extraction of one job in one workgroup (L <= 2^14)
+#include <cstring>
+
+#include "field.h"
+#include "kernels.h"
+
+// The file is compiled once per part (NTT_PART = 0..4) so that the template
+// instantiations build in parallel; without NTT_PART everything is built.
+#ifndef NTT_PART
+#define NTT_PART -1
+#endif
+#define NTT_HAS(k) (NTT_PART < 0 || NTT_PART == (k))
+
+namespace ext {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ inline uint32_t getbit(const uint64_t *b, uint64_t i) {
+    return (uint32_t)(b[i >> 6] >> (i & 63)) & 1u;
+}
+
+__device__ inline uint32_t emb_bit(const Emb &e, uint64_t i, uint64_t L) {
+    if (e.mode == EMB_PREFIX) return i < e.len ? getbit(e.bits, i) : 0u;
+    if (e.mode == EMB_SEED) {
+        uint64_t k = i + e.a;
+        if (k >= L) k -= L;
+        if (k >= e.N) return 0u;
+        uint64_t s = k + e.rot;
+        if (s >= e.N) s -= e.N;
+        return getbit(e.bits, s);
+    }
+    if (i >= e.N) return 0u;
+    uint64_t j = i ? e.N - i : 0;
+    return j < e.len ? getbit(e.bits, j) : 0u;
+}
+
+template <int N>
+__host__ __device__ constexpr int bitrev(int i) {
+    int r = 0;
+    for (int b = 1; b < N; b <<= 1) {
+        r = (r << 1) | (i & 1);
+        i >>= 1;
+    }
+    return r;
+}
+
+template <class F, int RAD>
+struct RootConst {
+    static constexpr RootsOf<F, RAD> tab{};
+};
+
+// In-register RAD-point DFT, forward (w_RAD^(t k)) or inverse (w_RAD^-(t k)).
+// Iterative radix-2 on bit-reversed input; constants are compile-time.
+template <class F, int RAD>
+__device__ inline void dft_reg(typename F::T *v, bool inv) {
+    using T = typename F::T;
+    constexpr RootsOf<F, RAD> rt{};
+    T u[RAD];
+#pragma unroll
+    for (int i = 0; i < RAD; ++i) u[bitrev<RAD>(i)] = v[i];
+#pragma unroll
+    for (int len = 2; len <= RAD; len <<= 1) {
+#pragma unroll
+        for (int s = 0; s < RAD; s += len) {
+#pragma unroll
+            for (int k = 0; k < len / 2; ++k) {
+                T a = u[s + k];
+                T b = u[s + k + len / 2];
+                if (k) b = F::mul_tw(b, rt.w[k * (RAD / len)]);
+                u[s + k] = F::add(a, b);
+                u[s + k + len / 2] = F::sub(a, b);
+            }
+        }
+    }
+    // inverse DFT = forward DFT with outputs k and RAD - k exchanged
+#pragma unroll
+    for (int k = 0; k < RAD; ++k) v[k] = u[inv ? ((RAD - k) & (RAD - 1)) : k];
+}
+
+// Twiddle w_max^E (E < 2^LGMAX) from the two-level tables.
+template <class F>
+__device__ inline typename F::T twiddle(const Tables &tb, uint64_t E) {
+    using T = typename F::T;
+    const T *lo = (const T *)tb.lo;
+    const T *hi = (const T *)tb.hi;
+    return F::tw_combine(hi[E >> 16], lo[E & 0xFFFF]);
+}
+
+// ------------------------------------------------------------------ tile geometry
+
+template <class F, int LGR, bool STRIDED>
+struct Tile {
+    using T = typename F::T;
+    static constexpr int R = 1 << LGR;
+    static constexpr int C = STRIDED ? (F::WORD_BITS == 32 ? 16 : 8) : (R >= 2048 ? 1 : 2048 / R);
+    static constexpr int NT0 = C * R / 16;
+    static constexpr int NT = NT0 > 1024 ? 1024 : NT0;
+    static constexpr int EPT = C * R / NT;
+    static constexpr int RF = (LGR % 4) ? (1 << (LGR % 4)) : 16;
+    static constexpr int NSTEPS = (LGR + 3) / 4;
+    static_assert(EPT >= 16 && EPT % 16 == 0, "tile too small");
+    static_assert(NT % 64 == 0 || NT < 64, "whole waves");
+
+    __device__ static inline int lidx(int c, int r) { return STRIDED ? r * C + c : c * R + r; }
+    template <int RAD>
+    __device__ static inline void coords(int q, int &c, int &j) {
+        int g = (int)threadIdx.x + q * NT;
+        if (STRIDED) {
+            c = g % C;
+            j = g / C;
+        } else {
+            j = g % (R / RAD);
+            c = g / (R / RAD);
+        }
+    }
+    // radix and span of step s
+    __host__ __device__ static constexpr int radix(int s, bool inv) {
+        return inv ? (s == NSTEPS - 1 ? RF : 16) : (s == 0 ? RF : 16);
+    }
+    __host__ __device__ static constexpr int span(int s, bool inv) {
+        int ns = 1;
+        for (int i = 0; i < s; ++i) ns *= radix(i, inv);
+        return ns;
+    }
+};
+
+// Stockham step compute on registers v (EPT values = EPT/RAD groups of RAD).
+template <class F, class Tl, int RAD>
+__device__ inline void step_compute(typename F::T *v, int Ns, bool inv, const Tables &tb) {
+    using T = typename F::T;
+    const T *twin = (const T *)tb.in;
+    constexpr int GPT = Tl::EPT / RAD;
+#pragma unroll
+    for (int q = 0; q < GPT; ++q) {
+        int c, j;
+        Tl::template coords<RAD>(q, c, j);
+        (void)c;
+        if (Ns > 1) {
+            int jm = j & (Ns - 1);
+            int scale = (1 << TWIN_LG) / (Ns * RAD);
+#pragma unroll
+            for (int t = 1; t < RAD; ++t) {
+                int e = t * jm * scale;
+                if (inv) e = ((1 << TWIN_LG) - e) & ((1 << TWIN_LG) - 1);
+                v[q * RAD + t] = F::mul_tw(v[q * RAD + t], twin[e]);
+            }
+        }
+        dft_reg<F, RAD>(&v[q * RAD], inv);
+    }
+}
+
+template <class F, class Tl, int RAD>
+__device__ inline void step_load_lds(typename F::T *v, const typename F::T *lds) {
+    constexpr int GPT = Tl::EPT / RAD;
+#pragma unroll
+    for (int q = 0; q < GPT; ++q) {
+        int c, j;
+        Tl::template coords<RAD>(q, c, j);
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) v[q * RAD + t] = lds[Tl::lidx(c, j + t * (Tl::R / RAD))];
+    }
+}
+
+template <class F, class Tl, int RAD>
+__device__ inline void step_store_lds(const typename F::T *v, typename F::T *lds, int Ns) {
+    constexpr int GPT = Tl::EPT / RAD;
+#pragma unroll
+    for (int q = 0; q < GPT; ++q) {
+        int c, j;
+        Tl::template coords<RAD>(q, c, j);
+        int jm = j & (Ns - 1);
+        int d = (j - jm) * RAD + jm;
+#pragma unroll
+        for (int t = 0; t < RAD; ++t) lds[Tl::lidx(c, d + t * Ns)] = v[q * RAD + t];
+    }
+}
+
+// Run steps [s0, s1) of a transform whose inputs for step s0 are already in
+// registers; the outputs of step s1-1 stay in registers (positions of the
+// last-step layout if s1 == NSTEPS). LDS exchanges in between.
+template <class F, class Tl, bool INV, int S>
+__device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, const Tables &tb) {
+    if constexpr (S < Tl::NSTEPS) {
+        constexpr int RAD = Tl::radix(S, INV);
+        constexpr int NS = Tl::span(S, INV);
+        if constexpr (S > 0) {
+            // inputs of this step come from LDS, written by the previous step
+            step_load_lds<F, Tl, RAD>(v, lds);
+        }
+        step_compute<F, Tl, RAD>(v, NS, INV, tb);
+        if constexpr (S + 1 < Tl::NSTEPS) {
+            __syncthreads();  // every read of the previous layout is done
+            step_store_lds<F, Tl, RAD>(v, lds, NS);
+            __syncthreads();
+            run_steps_from<F, Tl, INV, S + 1>(v, lds, tb);
+        }
+    }
+}
+
+template <class Tl, bool INV>
+struct Ends {
+    static constexpr int RAD_FIRST = Tl::radix(0, INV);
+    static constexpr int RAD_LAST = Tl::radix(Tl::NSTEPS - 1, INV);
+};
+
+// ------------------------------------------------------------------ strided pass
+
+struct KArgs {
+    const JobDev *jobs;
+    JobDev one;
+    Tables tb;
+    uint64_t S, Mprev;
+    int which;
+};
+
+template <class F, int LGR, int MODE>
+__global__ void __launch_bounds__((Tile<F, LGR, true>::NT)) k_strided(KArgs a) {
+    using Tl = Tile<F, LGR, true>;
+    using T = typename F::T;
+    constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
+    constexpr bool INV = (MODE == S_INV || MODE == S_INV_PARITY);
+    __shared__ T lds[C * R];
+
+    const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
+    T *data = (T *)(a.which ? J.B : J.A);
+    const uint64_t colTiles = a.S / C;
+    const uint64_t tile = blockIdx.x;
+    const uint64_t blk = tile / colTiles, ct = tile - blk * colTiles;
+    const uint64_t base = blk * a.Mprev + ct * C;
+    const int shift = F::LGMAX - (63 - __builtin_clzll(a.Mprev));  // 2^LGMAX / Mprev = 2^shift
+    const uint64_t emask = (uint64_t(1) << F::LGMAX) - 1;
+
+    T v[EPT];
+    {
+        constexpr int RAD = Ends<Tl, INV>::RAD_FIRST;
+        constexpr int GPT = EPT / RAD;
+#pragma unroll
+        for (int q = 0; q < GPT; ++q) {
+            int c, j;
+            Tl::template coords<RAD>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) {
+                const int r = j + t * (R / RAD);
+                const uint64_t gi = base + (uint64_t)r * a.S + c;
+                T x;
+                if constexpr (MODE == S_FWD_BITS) {
+                    const Emb &e = a.which ? J.ey : J.ex;
+                    x = F::from_bit(emb_bit(e, gi, J.L));
+                } else {
+                    x = data[gi];
+                }
+                if constexpr (INV) {
+                    uint64_t E = ((ct * C + c) * (uint64_t)r) << shift;
+                    x = F::mul_tw(x, twiddle<F>(a.tb, (uint64_t(0) - E) & emask));
+                }
+                v[q * RAD + t] = x;
+            }
+        }
+    }
+    run_steps_from<F, Tl, INV, 0>(v, lds, a.tb);
+    {
+        constexpr int RAD = Ends<Tl, INV>::RAD_LAST;
+        constexpr int GPT = EPT / RAD;
+#pragma unroll
+        for (int q = 0; q < GPT; ++q) {
+            int c, j;
+            Tl::template coords<RAD>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) {
+                const int r = j + t * (R / RAD);
+                const uint64_t gi = base + (uint64_t)r * a.S + c;
+                T x = v[q * RAD + t];
+                if constexpr (MODE == S_FWD || MODE == S_FWD_BITS) {
+                    uint64_t E = ((ct * C + c) * (uint64_t)r) << shift;
+                    data[gi] = F::mul_tw(x, twiddle<F>(a.tb, E));
+                } else if constexpr (MODE == S_INV) {
+                    data[gi] = x;
+                } else {
+                    // level 0 of the inverse: gi is the coefficient index. C
+                    // consecutive lanes hold C consecutive coefficients.
+                    uint32_t b = (uint32_t)(F::canon(x) & 1u);
+                    uint64_t mask = __ballot(b);
+                    const int lane = (int)(threadIdx.x & 63);
+                    if (c == 0 && gi < J.out_len) {
+                        uint64_t unit = (mask >> (lane & ~(C - 1))) & ((uint64_t(1) << C) - 1);
+                        const uint64_t rem = J.out_len - gi;
+                        if (rem < (uint64_t)C) unit &= (uint64_t(1) << rem) - 1;
+                        if constexpr (C == 8)
+                            ((uint8_t *)J.pb)[gi >> 3] = (uint8_t)unit;
+                        else
+                            ((uint16_t *)J.pb)[gi >> 4] = (uint16_t)unit;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ contiguous pass
+
+template <class F, int LGR, int MODE>
+__global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
+    using Tl = Tile<F, LGR, false>;
+    using T = typename F::T;
+    constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
+    __shared__ T lds[C * R];
+
+    const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
+    T *data = (T *)((MODE == C_FUSED || a.which) ? J.B : J.A);
+    const T *spec = (const T *)J.A;
+    const uint64_t base = (uint64_t)blockIdx.x * C * R;
+
+    T v[EPT];
+    {
+        constexpr int RAD = Ends<Tl, false>::RAD_FIRST;
+        constexpr int GPT = EPT / RAD;
+#pragma unroll
+        for (int q = 0; q < GPT; ++q) {
+            int c, j;
+            Tl::template coords<RAD>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) v[q * RAD + t] = data[base + (uint64_t)c * R + j + t * (R / RAD)];
+        }
+    }
+    run_steps_from<F, Tl, false, 0>(v, lds, a.tb);
+    constexpr int RADL = Ends<Tl, false>::RAD_LAST;
+    constexpr int GPTL = EPT / RADL;
+    if constexpr (MODE == C_FUSED) {
+        static_assert(Ends<Tl, true>::RAD_FIRST == RADL, "register hand-over needs equal radices");
+        const T K = (T)J.K;
+#pragma unroll
+        for (int q = 0; q < GPTL; ++q) {
+            int c, j;
+            Tl::template coords<RADL>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RADL; ++t) {
+                T x = spec[base + (uint64_t)c * R + j + t * (R / RADL)];
+                v[q * RADL + t] = F::mont(F::mont(v[q * RADL + t], x), K);
+            }
+        }
+        __syncthreads();  // LDS is reused by the inverse steps
+        run_steps_from<F, Tl, true, 0>(v, lds, a.tb);
+        constexpr int RADI = Ends<Tl, true>::RAD_LAST;
+#pragma unroll
+        for (int q = 0; q < EPT / RADI; ++q) {
+            int c, j;
+            Tl::template coords<RADI>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RADI; ++t) data[base + (uint64_t)c * R + j + t * (R / RADI)] = v[q * RADI + t];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < GPTL; ++q) {
+            int c, j;
+            Tl::template coords<RADL>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RADL; ++t) data[base + (uint64_t)c * R + j + t * (R / RADL)] = v[q * RADL + t];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ small: one job per workgroup
+
+template <int LG>
+struct SmallTile {
+    static constexpr int R = 1 << LG;
+    static constexpr int C = 1;
+    static constexpr int NT = R / 16;  // 16 values per thread (a partial wave for L < 2^10)
+    static constexpr int EPT = R / NT;
+    static constexpr int RF = (LG % 4) ? (1 << (LG % 4)) : 16;
+    static constexpr int NSTEPS = (LG + 3) / 4;
+    __device__ static inline int lidx(int c, int r) { return r; }
+    template <int RAD>
+    __device__ static inline void coords(int q, int &c, int &j) {
+        c = 0;
+        j = (int)threadIdx.x + q * NT;
+    }
+    __host__ __device__ static constexpr int radix(int s, bool inv) {
+        return inv ? (s == NSTEPS - 1 ? RF : 16) : (s == 0 ? RF : 16);
+    }
+    __host__ __device__ static constexpr int span(int s, bool inv) {
+        int ns = 1;
+        for (int i = 0; i < s; ++i) ns *= radix(i, inv);
+        return ns;
+    }
+};
+
+template <int LG>
+__global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs, JobDev one, Tables tb) {
+    using F = FBB;
+    using Tl = SmallTile<LG>;
+    using T = uint32_t;
+    constexpr int R = Tl::R, EPT = Tl::EPT, NT = Tl::NT;
+    __shared__ T lds[R];
+    __shared__ uint32_t red[2];
+
+    const JobDev &J = jobs ? jobs[blockIdx.x] : one;
+    constexpr int RAD0 = Ends<Tl, false>::RAD_FIRST;
+    constexpr int RADL = Ends<Tl, false>::RAD_LAST;
+
+    T va[EPT], vb[EPT];
+    // input transform
+#pragma unroll
+    for (int q = 0; q < EPT / RAD0; ++q) {
+        int c, j;
+        Tl::template coords<RAD0>(q, c, j);
+#pragma unroll
+        for (int t = 0; t < RAD0; ++t) va[q * RAD0 + t] = emb_bit(J.ex, j + t * (R / RAD0), J.L);
+    }
+    run_steps_from<F, Tl, false, 0>(va, lds, tb);
+    __syncthreads();
+    // seed transform
+#pragma unroll
+    for (int q = 0; q < EPT / RAD0; ++q) {
+        int c, j;
+        Tl::template coords<RAD0>(q, c, j);
+#pragma unroll
+        for (int t = 0; t < RAD0; ++t) vb[q * RAD0 + t] = emb_bit(J.ey, j + t * (R / RAD0), J.L);
+    }
+    run_steps_from<F, Tl, false, 0>(vb, lds, tb);
+    const T K = (T)J.K;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) vb[i] = F::mont(F::mont(vb[i], va[i]), K);
+    __syncthreads();
+    run_steps_from<F, Tl, true, 0>(vb, lds, tb);
+    constexpr int RADI = Ends<Tl, true>::RAD_LAST;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EPT / RADI; ++q) {
+        int c, j;
+        Tl::template coords<RADI>(q, c, j);
+#pragma unroll
+        for (int t = 0; t < RADI; ++t) lds[j + t * (R / RADI)] = vb[q * RADI + t];
+    }
+    // degenerate check (Dodis): any one bit and any zero bit among x_0..x_{n-1}
+    if (threadIdx.x < 2) red[threadIdx.x] = 0;
+    __syncthreads();
+    if (J.degen_n) {
+        const uint64_t nw = (J.degen_n + 63) >> 6;
+        uint32_t one_ = 0, zero_ = 0;
+        for (uint64_t w = threadIdx.x; w < nw; w += NT) {
+            uint64_t x = J.ex.bits[w];
+            uint64_t mk = (w + 1 < nw || (J.degen_n & 63) == 0) ? ~0ull : ((1ull << (J.degen_n & 63)) - 1);
+            one_ |= (x & mk) != 0;
+            zero_ |= (~x & mk) != 0;
+        }
+        if (one_) atomicOr(&red[0], 1u);
+        if (zero_) atomicOr(&red[1], 1u);
+    }
+    __syncthreads();
+    const bool degen = J.degen_n && (red[0] == 0 || red[1] == 0);
+    // parity, fold, pack: thread per output word
+    const uint64_t nwm = (J.m + 63) >> 6;
+    for (uint64_t w = threadIdx.x; w < nwm; w += NT) {
+        uint64_t word = 0;
+        if (!degen) {
+            for (int b = 0; b < 64; ++b) {
+                uint64_t i = w * 64 + b;
+                if (i >= J.m) break;
+                uint32_t bit = lds[i] & 1u;
+                if (J.nfold) bit ^= lds[i + J.nfold] & 1u;
+                word |= (uint64_t)bit << b;
+            }
+        }
+        J.z[w] = word;
+    }
+    if (threadIdx.x == 0 && J.status) *J.status = degen ? -3 : 0;
+}
+
+#if NTT_HAS(4)
+// ------------------------------------------------------------------ pack, degenerate check
+
+__global__ void __launch_bounds__(256) k_pack(const JobDev *jobs, JobDev one) {
+    const JobDev &J = jobs ? jobs[blockIdx.y] : one;
+    const uint64_t nwm = (J.m + 63) >> 6;
+    const uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool degen = J.degen_n && (J.flags[0] == 0 || J.flags[1] == 0);
+    if (w < nwm) {
+        uint64_t word = J.pb[w];
+        if (J.nfold) {
+            const uint64_t off = J.nfold + w * 64;
+            const uint64_t q = off >> 6, b = off & 63;
+            word ^= b ? ((J.pb[q] >> b) | (J.pb[q + 1] << (64 - b))) : J.pb[q];
+        }
+        const uint64_t rem = J.m - w * 64;
+        if (rem < 64) word &= (1ull << rem) - 1;
+        J.z[w] = degen ? 0ull : word;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && J.status) *J.status = degen ? -3 : 0;
+}
+
+__global__ void __launch_bounds__(256) k_degen(const JobDev *jobs, JobDev one) {
+    const JobDev &J = jobs ? jobs[blockIdx.x] : one;
+    __shared__ uint32_t red[2];
+    if (threadIdx.x < 2) red[threadIdx.x] = 0;
+    __syncthreads();
+    if (J.degen_n) {
+        const uint64_t nw = (J.degen_n + 63) >> 6;
+        uint32_t one_ = 0, zero_ = 0;
+        for (uint64_t w = threadIdx.x; w < nw; w += 256) {
+            uint64_t x = J.ex.bits[w];
+            uint64_t mk = (w + 1 < nw || (J.degen_n & 63) == 0) ? ~0ull : ((1ull << (J.degen_n & 63)) - 1);
+            one_ |= (x & mk) != 0;
+            zero_ |= (~x & mk) != 0;
+        }
+        if (one_) atomicOr(&red[0], 1u);
+        if (zero_) atomicOr(&red[1], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) J.flags[threadIdx.x] = red[threadIdx.x];
+}
+
+#endif
+
+// ------------------------------------------------------------------ launchers
+
+static KArgs make_args(const PassLaunch &p, const Tables &t) {
+    KArgs ka;
+    ka.jobs = p.jobs;
+    if (p.one) ka.one = *p.one;
+    else std::memset(&ka.one, 0, sizeof(ka.one));
+    ka.tb = t;
+    ka.S = p.S;
+    ka.Mprev = p.Mprev;
+    ka.which = p.which;
+    return ka;
+}
+
+template <class F, int LGR>
+static hipError_t strided_one(const PassLaunch &p, const KArgs &ka, hipStream_t s) {
+    using Tl = Tile<F, LGR, true>;
+    dim3 grid((unsigned)p.tiles, p.njobs), block(Tl::NT);
+    switch (p.mode) {
+        case S_FWD_BITS: hipLaunchKernelGGL((k_strided<F, LGR, S_FWD_BITS>), grid, block, 0, s, ka); break;
+        case S_FWD: hipLaunchKernelGGL((k_strided<F, LGR, S_FWD>), grid, block, 0, s, ka); break;
+        case S_INV: hipLaunchKernelGGL((k_strided<F, LGR, S_INV>), grid, block, 0, s, ka); break;
+        default: hipLaunchKernelGGL((k_strided<F, LGR, S_INV_PARITY>), grid, block, 0, s, ka); break;
+    }
+    return hipGetLastError();
+}
+
+template <class F, int LGR>
+static hipError_t contig_one(const PassLaunch &p, const KArgs &ka, hipStream_t s) {
+    using Tl = Tile<F, LGR, false>;
+    dim3 grid((unsigned)p.tiles, p.njobs), block(Tl::NT);
+    if (p.mode == C_FUSED)
+        hipLaunchKernelGGL((k_contig<F, LGR, C_FUSED>), grid, block, 0, s, ka);
+    else
+        hipLaunchKernelGGL((k_contig<F, LGR, C_FWD>), grid, block, 0, s, ka);
+    return hipGetLastError();
+}
+
+constexpr int BB_STRIDED_MAX = 11, BB_CONTIG_MAX = 14, GL_STRIDED_MAX = 10, GL_CONTIG_MAX = 12;
+constexpr int SMALL_MAX = 14;
+
+hipError_t launch_strided_bb(const PassLaunch &p, const Tables &t, hipStream_t s);
+hipError_t launch_strided_gl(const PassLaunch &p, const Tables &t, hipStream_t s);
+hipError_t launch_contig_bb(const PassLaunch &p, const Tables &t, hipStream_t s);
+hipError_t launch_contig_gl(const PassLaunch &p, const Tables &t, hipStream_t s);
+
+#if NTT_HAS(0)
+hipError_t launch_strided_bb(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    KArgs ka = make_args(p, t);
+    switch (p.lgr) {
+        case 7: return strided_one<FBB, 7>(p, ka, s);
+        case 8: return strided_one<FBB, 8>(p, ka, s);
+        case 9: return strided_one<FBB, 9>(p, ka, s);
+        case 10: return strided_one<FBB, 10>(p, ka, s);
+        case 11: return strided_one<FBB, 11>(p, ka, s);
+    }
+    return hipErrorInvalidValue;
+}
+#endif
+
+#if NTT_HAS(1)
+hipError_t launch_strided_gl(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    KArgs ka = make_args(p, t);
+    switch (p.lgr) {
+        case 7: return strided_one<FGL, 7>(p, ka, s);
+        case 8: return strided_one<FGL, 8>(p, ka, s);
+        case 9: return strided_one<FGL, 9>(p, ka, s);
+        case 10: return strided_one<FGL, 10>(p, ka, s);
+    }
+    return hipErrorInvalidValue;
+}
+#endif
+
+#if NTT_HAS(2)
+hipError_t launch_contig_bb(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    KArgs ka = make_args(p, t);
+    switch (p.lgr) {
+        case 7: return contig_one<FBB, 7>(p, ka, s);
+        case 8: return contig_one<FBB, 8>(p, ka, s);
+        case 9: return contig_one<FBB, 9>(p, ka, s);
+        case 10: return contig_one<FBB, 10>(p, ka, s);
+        case 11: return contig_one<FBB, 11>(p, ka, s);
+        case 12: return contig_one<FBB, 12>(p, ka, s);
+        case 13: return contig_one<FBB, 13>(p, ka, s);
+        case 14: return contig_one<FBB, 14>(p, ka, s);
+    }
+    return hipErrorInvalidValue;
+}
+#endif
+
+#if NTT_HAS(3)
+hipError_t launch_contig_gl(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    KArgs ka = make_args(p, t);
+    switch (p.lgr) {
+        case 7: return contig_one<FGL, 7>(p, ka, s);
+        case 8: return contig_one<FGL, 8>(p, ka, s);
+        case 9: return contig_one<FGL, 9>(p, ka, s);
+        case 10: return contig_one<FGL, 10>(p, ka, s);
+        case 11: return contig_one<FGL, 11>(p, ka, s);
+        case 12: return contig_one<FGL, 12>(p, ka, s);
+    }
+    return hipErrorInvalidValue;
+}
+#endif
+
+#if NTT_HAS(4)
+int max_strided_lg(int field) { return field == FIELD_BB ? BB_STRIDED_MAX : GL_STRIDED_MAX; }
+int max_contig_lg(int field) { return field == FIELD_BB ? BB_CONTIG_MAX : GL_CONTIG_MAX; }
+int max_small_lg() { return SMALL_MAX; }
+
+template <class F>
+static Geometry geo_s(int lgr) {
+    switch (lgr) {
+#define G(L) case L: return Geometry{Tile<F, L, true>::C, Tile<F, L, true>::NT};
+        G(7) G(8) G(9) G(10) G(11)
+#undef G
+    }
+    return Geometry{0, 0};
+}
+template <class F>
+static Geometry geo_c(int lgr) {
+    switch (lgr) {
+#define G(L) case L: return Geometry{Tile<F, L, false>::C, Tile<F, L, false>::NT};
+        G(7) G(8) G(9) G(10) G(11) G(12) G(13) G(14)
+#undef G
+    }
+    return Geometry{0, 0};
+}
+Geometry strided_geometry(int field, int lgr) { return field == FIELD_BB ? geo_s<FBB>(lgr) : geo_s<FGL>(lgr); }
+Geometry contig_geometry(int field, int lgr) { return field == FIELD_BB ? geo_c<FBB>(lgr) : geo_c<FGL>(lgr); }
+
+hipError_t launch_strided(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    return p.field == FIELD_BB ? launch_strided_bb(p, t, s) : launch_strided_gl(p, t, s);
+}
+hipError_t launch_contig(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    return p.field == FIELD_BB ? launch_contig_bb(p, t, s) : launch_contig_gl(p, t, s);
+}
+
+template <int LG>
+static hipError_t small_one(uint32_t njobs, const JobDev *jobs, const JobDev *one, const Tables &t, hipStream_t s) {
+    JobDev o;
+    if (one) o = *one;
+    else std::memset(&o, 0, sizeof(o));
+    hipLaunchKernelGGL((k_small<LG>), dim3(njobs), dim3(SmallTile<LG>::NT), 0, s, jobs, o, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_small(int lg, uint32_t njobs, const JobDev *jobs, const JobDev *one, const Tables &t,
+                        hipStream_t s) {
+    switch (lg) {
+        case 6: return small_one<6>(njobs, jobs, one, t, s);
+        case 7: return small_one<7>(njobs, jobs, one, t, s);
+        case 8: return small_one<8>(njobs, jobs, one, t, s);
+        case 9: return small_one<9>(njobs, jobs, one, t, s);
+        case 10: return small_one<10>(njobs, jobs, one, t, s);
+        case 11: return small_one<11>(njobs, jobs, one, t, s);
+        case 12: return small_one<12>(njobs, jobs, one, t, s);
+        case 13: return small_one<13>(njobs, jobs, one, t, s);
+        case 14: return small_one<14>(njobs, jobs, one, t, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, const JobDev *one, hipStream_t s) {
+    JobDev o;
+    if (one) o = *one;
+    else std::memset(&o, 0, sizeof(o));
+    unsigned gx = (unsigned)((max_words + 255) / 256);
+    if (gx == 0) gx = 1;
+    hipLaunchKernelGGL(k_pack, dim3(gx, njobs), dim3(256), 0, s, jobs, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_degen(uint32_t njobs, const JobDev *jobs, const JobDev *one, hipStream_t s) {
+    JobDev o;
+    if (one) o = *one;
+    else std::memset(&o, 0, sizeof(o));
+    hipLaunchKernelGGL(k_degen, dim3(njobs), dim3(256), 0, s, jobs, o);
+    return hipGetLastError();
+}
+#endif
+
+}  // namespace ext

@@ -1,0 +1,146 @@
+"""GPU parity: the HIP path against the oracle, bit for bit, through the C-ABI."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import gpu_extract, show_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2402_09481_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_gl():
+    """A context that runs every shape on the 64-bit field (checks that path at small sizes)."""
+    import paper_2402_09481_amd as P
+    os.environ["EXT_FORCE_FIELD"] = "gl"
+    try:
+        c = P.Context(0)
+    finally:
+        del os.environ["EXT_FORCE_FIELD"]
+    yield c
+    c.close()
+
+
+def seed_len(kind, n, m):
+    return {"toeplitz": n + m - 1, "circulant": n + 1, "dodis": n}[kind]
+
+
+def run_case(ctx, kind, n, m, order="paper", seed=0, px=0.5):
+    g = W.rng(seed)
+    x = W.bernoulli_bits(g, n, px)
+    y = W.bernoulli_bits(g, seed_len(kind, n, m), 0.5)
+    if kind == "dodis":
+        x[0] = (int(x[0]) | 1) & ~2  # x_0 = 1, x_1 = 0: never degenerate
+    show_case(kind, n, m, order, seed)
+    code, z = gpu_extract(ctx, kind, x, y, n, m, order)
+    assert code == 0, (kind, n, m, code)
+    rc, want = oracle.extract(kind, x, y, n, m, order)
+    assert rc == 0
+    assert z.shape == want.shape
+    bad = np.nonzero(z != want)[0]
+    assert bad.size == 0, "first bad word %d of %d (%s n=%d m=%d)" % (bad[0], z.size, kind, n, m)
+
+
+def test_toeplitz_small_workload(ctx):
+    j = W.toeplitz_small()
+    show_case("toeplitz_small")
+    code, z = gpu_extract(ctx, "toeplitz", j.x, j.y, j.n, j.m, "linear")
+    rc, want = oracle.extract("toeplitz", j.x, j.y, j.n, j.m, "linear")
+    assert code == 0 and rc == 0 and (z == want).all()
+
+
+@pytest.mark.parametrize("order", ["paper", "linear"])
+def test_toeplitz_tiny_all_shapes(ctx, order):
+    for n in list(range(1, 20)) + [63, 64, 65, 127, 128, 129]:
+        for m in sorted({v for v in (1, 2, n // 2, n - 1, n) if 1 <= v <= n}):
+            run_case(ctx, "toeplitz", n, m, order, seed=n * 1000 + m)
+
+
+@pytest.mark.parametrize("n,m", [(2000, 1000), (4096, 4096), (5000, 3191), (8192, 1), (8191, 8191),
+                                 (9000, 4500), (12345, 4000)])
+def test_toeplitz_single_workgroup_sizes(ctx, n, m):
+    run_case(ctx, "toeplitz", n, m, "paper", seed=n + m)
+    run_case(ctx, "toeplitz", n, m, "linear", seed=n + m + 1)
+
+
+@pytest.mark.parametrize("n,m", [(8193, 8193), (20000, 7777), (40000, 20000), (65536, 65536), (100003, 50001),
+                                 (300000, 1000), (1 << 19, 1 << 18)])
+def test_toeplitz_multipass_32bit(ctx, n, m):
+    run_case(ctx, "toeplitz", n, m, "paper", seed=7 * n + m, px=0.4)
+
+
+@pytest.mark.parametrize("n,m", [(11, 5), (13, 13), (61, 60), (1019, 500), (4099, 4099), (8219, 8000),
+                                 (16421, 9000), (65587, 32768)])
+def test_dodis(ctx, n, m):
+    assert oracle.is_na_prime(n)
+    run_case(ctx, "dodis", n, m, seed=n, px=0.3)
+
+
+@pytest.mark.parametrize("n_in,m", [(10, 10), (12, 6), (100, 99), (1018, 1018), (4098, 2049), (8218, 8218),
+                                    (16420, 100), (65586, 65586)])
+def test_circulant(ctx, n_in, m):
+    assert oracle.is_na_prime(n_in + 1)
+    run_case(ctx, "circulant", n_in, m, seed=n_in)
+
+
+def test_dodis_workload(ctx):
+    j = W.dodis_2p20()
+    show_case("dodis_2p20")
+    code, z = gpu_extract(ctx, "dodis", j.x, j.y, j.n, j.m)
+    assert code == 0
+    rc, want = oracle.extract("dodis", j.x, j.y, j.n, j.m)
+    assert rc == 0 and (z == want).all()
+
+
+@pytest.mark.parametrize("kind,n,m", [("toeplitz", 9000, 7000), ("toeplitz", 100000, 50000),
+                                      ("dodis", 8219, 8219), ("circulant", 16420, 8000)])
+def test_64bit_field_path(ctx_gl, kind, n, m):
+    run_case(ctx_gl, kind, n, m, "paper", seed=3 * n + m)
+
+
+def test_dodis_degenerate_inputs(ctx):
+    n, m = 1019, 300
+    y = W.bernoulli_bits(W.rng(1), n, 0.5)
+    for x in (np.zeros(W.nwords(n), np.uint64), W.mask_tail(np.full(W.nwords(n), ~np.uint64(0)), n)):
+        show_case("degenerate", int(x[0] & np.uint64(1)))
+        code, z = gpu_extract(ctx, "dodis", x, y, n, m)
+        assert code == oracle.EDEGENERATE
+        assert not z.any()
+    # the same on the multi-pass path
+    n = 65587
+    y = W.bernoulli_bits(W.rng(2), n, 0.5)
+    x = W.mask_tail(np.full(W.nwords(n), ~np.uint64(0)), n)
+    code, z = gpu_extract(ctx, "dodis", x, y, n, 1000)
+    assert code == oracle.EDEGENERATE and not z.any()
+
+
+def test_host_side_errors(ctx):
+    import torch
+    x = torch.zeros(4, dtype=torch.int64, device="cuda")
+    y = torch.zeros(8, dtype=torch.int64, device="cuda")
+    z = torch.zeros(4, dtype=torch.int64, device="cuda")
+    assert ctx.extract("toeplitz", x, y, 100, 0, z=z, check=False)[0] == oracle.EINVAL
+    assert ctx.extract("toeplitz", x, y, 100, 101, z=z, check=False)[0] == oracle.EINVAL
+    assert ctx.extract("dodis", x, y, 100, 10, z=z, check=False)[0] == oracle.ENOTNA
+    assert ctx.extract("circulant", x, y, 11, 5, z=z, check=False)[0] == oracle.ENOTNA
+    assert ctx.extract("toeplitz", x, y, 100, 50, z=x, check=False)[0] == oracle.EINVAL  # z overlaps x
+
+
+def test_sync_flag_returns_status(ctx):
+    import torch
+    n, m = 1019, 64
+    x = torch.zeros(W.nwords(n), dtype=torch.int64, device="cuda")
+    y = torch.ones(W.nwords(n), dtype=torch.int64, device="cuda")
+    rc, _ = ctx.extract("dodis", x, y, n, m, sync=True, check=False)
+    assert rc == oracle.EDEGENERATE
