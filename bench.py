@@ -44,9 +44,15 @@ def kernel_bytes(label: str, L: int, w: int, n: int, N: int, m: int) -> int:
     strided mode 0 (embed bits): writes L words, reads the packed input (n or N bits);
     strided mode 1/2 and contiguous mode 0: read + write L words; contiguous mode 1
     (fused seed transform, product, inverse): reads 2L, writes L; strided mode 3
-    (last inverse pass): reads L words, writes m parity bits; pack: m bits in, m bits out."""
+    (last inverse pass): reads L words, writes m parity bits; pack: m bits in, m bits out;
+    embed: both packed inputs in, both L-bit coefficient strings out; ptrans: L parity bits
+    in and out."""
     if label.startswith("pack"):
         return 2 * (m // 8)
+    if label.startswith("embed"):  # both packed inputs in, two L-bit coefficient strings out
+        return (n + N) // 8 + 2 * (L // 8)
+    if label.startswith("ptrans"):  # L parity bits, tile-major in, natural order out
+        return 2 * (L // 8)
     kind = label.split("[")[0]
     fields = dict(kv.split("=") for kv in label.split("[")[1].rstrip("]").split(",")[1:])
     mode, arr = int(fields["mode"]), int(fields.get("arr", 0))
@@ -65,13 +71,15 @@ def kernel_bytes(label: str, L: int, w: int, n: int, N: int, m: int) -> int:
 def cpu_baseline(job, seconds: float):
     """Oracle rows of the same workload for about `seconds` of one core."""
     import oracle
+    # the row routine pays a setup (seed reversal) per call: fit setup + rows * per_row
     t0 = time.perf_counter()
-    oracle.toeplitz_rows(job.x, job.y, job.n, job.m, 0, 4, job.seed_order)
-    probe = time.perf_counter() - t0
-    rows = 4
-    # the row routine's setup (seed reversal) is paid per call; size the sample to the budget
-    per_row_guess = max(probe / 4, 1e-3)
-    rows = int(max(8, min(4096, seconds / per_row_guess)))
+    oracle.toeplitz_rows(job.x, job.y, job.n, job.m, 0, 2, job.seed_order)
+    t1 = time.perf_counter()
+    oracle.toeplitz_rows(job.x, job.y, job.n, job.m, 0, 34, job.seed_order)
+    t2 = time.perf_counter()
+    per_row = max(((t2 - t1) - (t1 - t0)) / 32, 1e-4)
+    setup = max((t1 - t0) - 2 * per_row, 0.0)
+    rows = int(max(8, min(1 << 16, (seconds - setup) / per_row)))
     t0 = time.perf_counter()
     oracle.toeplitz_rows(job.x, job.y, job.n, job.m, 0, rows, job.seed_order)
     dt = time.perf_counter() - t0
@@ -168,12 +176,25 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0 = skip)")
     ap.add_argument("--batched", action="store_true", help="also run the 4096-block batched comparison")
     ap.add_argument("--serving", action="store_true", help="also run a short serving sweep")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="run a plain device copy of this many GiB first (reference for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported (use --gpus 1)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.copy_calibration_gib > 0:
+        import torch
+        nb = int(args.copy_calibration_gib * (1 << 30))
+        src = torch.ones(nb // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read + %d bytes written per copy kernel" % (nb, nb))
+        del src, dst
+        torch.cuda.empty_cache()
     out, job = run_headline(args)
     if args.cpu_seconds > 0:
         log("cpu baseline (oracle, %.0f s budget)" % args.cpu_seconds)

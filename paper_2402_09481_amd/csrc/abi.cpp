@@ -173,7 +173,7 @@ constexpr int MIN_LG = 6;
 // are balanced and kept at or below the preferred size (LDS tile <= 64 KiB).
 bool split_levels(int field, int lg, Plan &p) {
     const int cap_c = max_contig_lg(field), cap_s = max_strided_lg(field);
-    const int pref_s = field == FIELD_BB ? 10 : cap_s;
+    const int pref_s = 9;  // strided tiles of 2^9 rows fit 64 KiB of LDS in both fields
     for (int k = 2; k <= 4; ++k) {
         if (lg < MIN_LEVEL_LG * k) return false;
         if (lg > cap_c + (k - 1) * cap_s) continue;
@@ -220,18 +220,23 @@ int make_plan(uint64_t Lmin, int force, Plan &p) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t a = 0, b = 0, pb = 0, flags = 0, total = 0;
+    size_t a = 0, b = 0, pb = 0, eb0 = 0, eb1 = 0, flags = 0, total = 0;
 };
 
+// A and B (L words each), the packed parity and the two embedded inputs (L bits
+// each, plus a spare word), and the degenerate-check flags.
 Layout workspace_layout(const Plan &p) {
     Layout l;
     if (p.small) return l;
     const size_t L = size_t(1) << p.lg;
     const size_t w = p.field == FIELD_BB ? 4 : 8;
+    const size_t bits = align256((L / 64 + 2) * 8);
     l.a = 0;
     l.b = align256(L * w);
     l.pb = l.b + align256(L * w);
-    l.flags = l.pb + align256((L / 64 + 2) * 8);
+    l.eb0 = l.pb + bits;
+    l.eb1 = l.eb0 + bits;
+    l.flags = l.eb1 + bits;
     l.total = l.flags + 256;
     return l;
 }
@@ -321,6 +326,8 @@ JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint6
         j.A = ws + l.a;
         j.B = ws + l.b;
         j.pb = (uint64_t *)(ws + l.pb);
+        j.eb[0] = (uint64_t *)(ws + l.eb0);
+        j.eb[1] = (uint64_t *)(ws + l.eb1);
         j.flags = (uint32_t *)(ws + l.flags);
     }
     j.z = z;
@@ -517,6 +524,10 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
     }
     const uint64_t L = uint64_t(1) << p.lg;
     hipError_t e;
+    tr.begin();
+    e = launch_embed(njobs, L, jobs_dev, one, s);
+    tr.end("embed");
+    if (e != hipSuccess) return e;
     for (int which = 0; which < 2; ++which) {
         uint64_t Mprev = L;
         for (int i = 0; i + 1 < p.nlev; ++i) {
@@ -582,6 +593,10 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, 1));
         if (e != hipSuccess) return e;
     }
+    tr.begin();
+    e = launch_ptrans(p.field, uint64_t(1) << p.lgr[0], L >> p.lgr[0], njobs, jobs_dev, one, s);
+    tr.end("ptrans");
+    if (e != hipSuccess) return e;
     if (any_degen && (e = launch_degen(njobs, jobs_dev, one, s)) != hipSuccess) return e;
     tr.begin();
     e = launch_pack(njobs, words(max_m), jobs_dev, one, s);

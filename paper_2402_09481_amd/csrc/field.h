@@ -61,6 +61,10 @@ struct FBB {
     __device__ static inline uint32_t tw_combine(uint32_t hi, uint32_t lo) { return mont(hi, lo); }
     __device__ static inline uint32_t canon(uint32_t a) { return a; }
     __device__ static inline uint32_t from_bit(uint32_t b) { return b; }
+    __device__ static inline uint32_t as_b(uint32_t v) { return v; }
+    // x * w_RAD^K with the root's Montgomery form as a compile-time constant
+    template <int RAD, int K>
+    __device__ static inline uint32_t mul_root(uint32_t x);
 
     // host/compile-time helpers
     __host__ __device__ static constexpr uint32_t mulmod(uint32_t a, uint32_t b) {
@@ -87,42 +91,86 @@ struct FGL {
     static constexpr uint64_t EPS = 0xFFFFFFFFull;  // 2^64 mod P
     static constexpr int LGMAX = 32;
     // order 2^32, chosen (as a power of 7^((P-1)/2^32), 7 generating the group) so
-    // that WMAX^(2^26) = 8: the 64th roots of unity are then powers of 2.
+    // that WMAX^(2^26) = 8: the 64th roots of unity are then powers of 2, and
+    // w_RAD^k = 2^(192 k / RAD) for RAD <= 64 (2^96 = -1, so 2 has order 192).
     static constexpr uint64_t WMAX = 5980198667562970375ull;
     static constexpr int WORD_BITS = 64;
 
-    // a + b for any 64-bit representatives: each wrap past 2^64 is worth EPS; the
-    // first correction can wrap once more, the second cannot.
+    // representative in [0, P): subtracting P is adding EPS mod 2^64
+    __device__ static inline uint64_t canon(uint64_t a) { return a + (a >= P ? EPS : 0ull); }
+    // a + b for any a < 2^64 and b < P: a single wrap past 2^64 (worth EPS) leaves
+    // a + b - 2^64 < P, so adding EPS cannot wrap again.
     __device__ static inline uint64_t add(uint64_t a, uint64_t b) {
-        uint64_t s, s2;
-        bool c = __builtin_add_overflow(a, b, &s);
-        bool c2 = __builtin_add_overflow(s, c ? EPS : 0ull, &s2);
-        return s2 + (c2 ? EPS : 0ull);
+        uint64_t s = a + b;
+        return s + (s < b ? EPS : 0ull);
     }
+    // a - b for any a < 2^64 and b < P: after a borrow a - b + 2^64 > EPS, so
+    // removing EPS (the value of the borrowed 2^64) cannot borrow again.
     __device__ static inline uint64_t sub(uint64_t a, uint64_t b) {
-        uint64_t d, d2;
-        bool c = __builtin_sub_overflow(a, b, &d);
-        bool c2 = __builtin_sub_overflow(d, c ? EPS : 0ull, &d2);
-        return d2 - (c2 ? EPS : 0ull);
+        uint64_t d = a - b;
+        return d - (a < b ? EPS : 0ull);
     }
-    // 128-bit x = x3*2^96 + x2*2^64 + (x1:x0)  ->  (x1:x0) - x3 + x2*(2^32 - 1)  (mod P)
-    __device__ static inline uint64_t reduce128(uint64_t hi, uint64_t lo) {
-        uint64_t x3 = hi >> 32, x2 = hi & EPS;
-        uint64_t t0;
-        if (__builtin_sub_overflow(lo, x3, &t0)) t0 -= EPS;  // t0 >= 2^64 - 2^32 + 1 here: no second wrap
-        uint64_t t1 = (x2 << 32) - x2;                      // x2 * EPS < 2^64
+    // 128-bit x = x3*2^96 + x2*2^64 + lo  ->  lo + x2*(2^32 - 1) - x3  (mod P)
+    __device__ static inline uint64_t reduce(uint32_t x3, uint32_t x2, uint64_t lo) {
         uint64_t r;
-        bool c = __builtin_add_overflow(t0, t1, &r);        // r <= 2^64 - 2^33 after a wrap
-        return r + (c ? EPS : 0ull);
+        // lo + x2*EPS < 2^65; a wrap leaves r <= 2^64 - 2^33, so +EPS cannot wrap
+        bool c = __builtin_add_overflow(lo, (uint64_t)x2 * EPS, &r);
+        r += c ? EPS : 0ull;
+        uint64_t d = r - (uint64_t)x3;
+        // after a borrow d = r - x3 + 2^64 > 2^64 - 2^32 > EPS: no second borrow
+        return d - (r < (uint64_t)x3 ? EPS : 0ull);
     }
+    __device__ static inline uint64_t reduce128(uint64_t hi, uint64_t lo) {
+        return reduce((uint32_t)(hi >> 32), (uint32_t)hi, lo);
+    }
+    // a * b mod P (result < 2^64, not necessarily canonical); schoolbook on 32-bit
+    // halves with 32x32+64 multiply-adds.
     __device__ static inline uint64_t mul(uint64_t a, uint64_t b) {
-        return reduce128(__umul64hi(a, b), a * b);
+        const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+        const uint64_t t00 = (uint64_t)a0 * b0;
+        const uint64_t t10 = (uint64_t)a1 * b0 + (t00 >> 32);
+        const uint64_t t01 = (uint64_t)a0 * b1 + (uint32_t)t10;
+        const uint64_t t11 = (uint64_t)a1 * b1 + (t10 >> 32) + (t01 >> 32);  // <= 2^64 - 1
+        const uint64_t lo = (t01 << 32) | (uint32_t)t00;
+        return reduce((uint32_t)(t11 >> 32), (uint32_t)t11, lo);
+    }
+    // x * 2^S mod P for a compile-time S (not necessarily canonical).
+    template <int S>
+    __device__ static inline uint64_t mul_pow2(uint64_t x) {
+        constexpr int s = ((S % 192) + 192) % 192;
+        if constexpr (s == 0) {
+            return x;
+        } else if constexpr (s >= 96) {  // 2^96 = -1
+            return P - canon(mul_pow2<s - 96>(x));
+        } else if constexpr (s < 32) {
+            // x 2^s = hi*2^64 + lo with hi < 2^32: lo + hi*EPS
+            uint64_t r;
+            bool c = __builtin_add_overflow(x << s, (uint64_t)(uint32_t)(x >> (64 - s)) * EPS, &r);
+            return r + (c ? EPS : 0ull);  // r < 2^63 after a wrap
+        } else if constexpr (s == 32) {
+            // x 2^32 = x1*2^64 + x0*2^32: (x0 << 32) + x1*EPS
+            uint64_t r;
+            bool c = __builtin_add_overflow(x << 32, (uint64_t)(uint32_t)(x >> 32) * EPS, &r);
+            return r + (c ? EPS : 0ull);
+        } else if constexpr (s < 64) {
+            return reduce128(x >> (64 - s), x << s);
+        } else {
+            // 64 <= s < 96: (x 2^(s-64)) 2^64 with 2^64 = 2^32 - 1: y 2^32 - y
+            const uint64_t y = canon(mul_pow2<s - 64>(x));
+            return sub(mul_pow2<32>(y), y);
+        }
+    }
+    // x * w_RAD^K (the compile-time roots of the in-register DFTs)
+    template <int RAD, int K>
+    __device__ static inline uint64_t mul_root(uint64_t x) {
+        return mul_pow2<(192 / RAD) * K>(x);
     }
     __device__ static inline uint64_t mont(uint64_t a, uint64_t b) { return mul(a, b); }
     __device__ static inline uint64_t mul_tw(uint64_t a, uint64_t tw) { return mul(a, tw); }
     __device__ static inline uint64_t tw_combine(uint64_t hi, uint64_t lo) { return mul(hi, lo); }
-    __device__ static inline uint64_t canon(uint64_t a) { return a >= P ? a - P : a; }
     __device__ static inline uint64_t from_bit(uint32_t b) { return b; }
+    // operand prepared for add/sub as their second argument
+    __device__ static inline uint64_t as_b(uint64_t v) { return canon(v); }
 
     __host__ __device__ static constexpr uint64_t mulmod(uint64_t a, uint64_t b) {
         return (uint64_t)((unsigned __int128)a * b % P);
@@ -138,6 +186,12 @@ struct FGL {
     }
     __host__ __device__ static constexpr uint64_t to_tw(uint64_t w) { return w; }
 };
+
+template <int RAD, int K>
+__device__ inline uint32_t FBB::mul_root(uint32_t x) {
+    constexpr uint32_t w = FBB::powmod(FBB::powmod(FBB::WMAX, (uint64_t(1) << FBB::LGMAX) / RAD), K);
+    return mont(x, FBB::to_tw(w));
+}
 
 // Compile-time table of the RAD-th roots of unity w_RAD^k (k < RAD) in twiddle form.
 template <class F, int RAD>

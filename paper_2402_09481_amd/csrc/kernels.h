@@ -34,6 +34,7 @@ struct JobDev {
     void *A;           // L words: the input transform, then its spectrum
     void *B;           // L words: the seed transform, then the product, then the convolution
     uint64_t *pb;      // packed parity of coefficients [0, out_len) (+1 spare word)
+    uint64_t *eb[2];   // the two embedded coefficient vectors as L-bit strings (multi-pass only)
     uint32_t *flags;   // degenerate check: flags[0] = any one bit, flags[1] = any zero bit
     uint64_t *z;       // caller's output, ceil(m/64) words
     int32_t *status;   // caller's status word or nullptr
@@ -91,6 +92,11 @@ hipError_t launch_small(int lg, uint32_t njobs, const JobDev *jobs, const JobDev
                         hipStream_t s);
 // Packed parity -> z (fold, mask, degenerate check result, status).
 hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, const JobDev *one, hipStream_t s);
+// Lay out both inputs as L-bit coefficient strings (eb[0], eb[1]).
+hipError_t launch_embed(uint32_t njobs, uint64_t max_L, const JobDev *jobs, const JobDev *one, hipStream_t s);
+// Tile-major parity units of the last inverse pass -> packed natural order (pb).
+hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint32_t njobs, const JobDev *jobs, const JobDev *one,
+                         hipStream_t s);
 // Dodis degenerate-input check (writes flags).
 hipError_t launch_degen(uint32_t njobs, const JobDev *jobs, const JobDev *one, hipStream_t s);
 

@@ -34,7 +34,9 @@
 //              L^-1, inverse row transform (last forward level of the seed,
 //              the pointwise product, first inverse level)
 //   small      whole extraction of one job in one workgroup (L <= 2^14)
+#include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "field.h"
 #include "kernels.h"
@@ -50,11 +52,13 @@ namespace ext {
 
 // ------------------------------------------------------------------ helpers
 
-__device__ inline uint32_t getbit(const uint64_t *b, uint64_t i) {
+__host__ __device__ inline uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
+__host__ __device__ inline uint32_t getbit(const uint64_t *b, uint64_t i) {
     return (uint32_t)(b[i >> 6] >> (i & 63)) & 1u;
 }
 
-__device__ inline uint32_t emb_bit(const Emb &e, uint64_t i, uint64_t L) {
+__host__ __device__ inline uint32_t emb_bit(const Emb &e, uint64_t i, uint64_t L) {
     if (e.mode == EMB_PREFIX) return i < e.len ? getbit(e.bits, i) : 0u;
     if (e.mode == EMB_SEED) {
         uint64_t k = i + e.a;
@@ -79,34 +83,42 @@ __host__ __device__ constexpr int bitrev(int i) {
     return r;
 }
 
-template <class F, int RAD>
-struct RootConst {
-    static constexpr RootsOf<F, RAD> tab{};
-};
-
 // In-register RAD-point DFT, forward (w_RAD^(t k)) or inverse (w_RAD^-(t k)).
-// Iterative radix-2 on bit-reversed input; constants are compile-time.
+// Iterative radix-2 decimation in time on bit-reversed input; the roots are
+// compile-time (for the 64-bit field they are powers of 2, applied by shifts).
+template <class F, int RAD, int LEN, int K>
+__device__ inline void dft_layer_k(typename F::T *u) {
+    if constexpr (K < LEN / 2) {
+#pragma unroll
+        for (int s = 0; s < RAD; s += LEN) {
+            typename F::T a = u[s + K];
+            typename F::T b = u[s + K + LEN / 2];
+            if constexpr (K == 0)
+                b = F::as_b(b);
+            else
+                b = F::as_b(F::template mul_root<LEN, K>(b));
+            u[s + K] = F::add(a, b);
+            u[s + K + LEN / 2] = F::sub(a, b);
+        }
+        dft_layer_k<F, RAD, LEN, K + 1>(u);
+    }
+}
+
+template <class F, int RAD, int LEN>
+__device__ inline void dft_layers(typename F::T *u) {
+    if constexpr (LEN <= RAD) {
+        dft_layer_k<F, RAD, LEN, 0>(u);
+        dft_layers<F, RAD, LEN * 2>(u);
+    }
+}
+
 template <class F, int RAD>
 __device__ inline void dft_reg(typename F::T *v, bool inv) {
     using T = typename F::T;
-    constexpr RootsOf<F, RAD> rt{};
     T u[RAD];
 #pragma unroll
     for (int i = 0; i < RAD; ++i) u[bitrev<RAD>(i)] = v[i];
-#pragma unroll
-    for (int len = 2; len <= RAD; len <<= 1) {
-#pragma unroll
-        for (int s = 0; s < RAD; s += len) {
-#pragma unroll
-            for (int k = 0; k < len / 2; ++k) {
-                T a = u[s + k];
-                T b = u[s + k + len / 2];
-                if (k) b = F::mul_tw(b, rt.w[k * (RAD / len)]);
-                u[s + k] = F::add(a, b);
-                u[s + k + len / 2] = F::sub(a, b);
-            }
-        }
-    }
+    dft_layers<F, RAD, 2>(u);
     // inverse DFT = forward DFT with outputs k and RAD - k exchanged
 #pragma unroll
     for (int k = 0; k < RAD; ++k) v[k] = u[inv ? ((RAD - k) & (RAD - 1)) : k];
@@ -127,7 +139,8 @@ template <class F, int LGR, bool STRIDED>
 struct Tile {
     using T = typename F::T;
     static constexpr int R = 1 << LGR;
-    static constexpr int C = STRIDED ? (F::WORD_BITS == 32 ? 16 : 8) : (R >= 2048 ? 1 : 2048 / R);
+    // strided tiles: C adjacent columns give 128-byte row segments in HBM
+    static constexpr int C = STRIDED ? (F::WORD_BITS == 32 ? 32 : 16) : (R >= 2048 ? 1 : 2048 / R);
     static constexpr int NT0 = C * R / 16;
     static constexpr int NT = NT0 > 1024 ? 1024 : NT0;
     static constexpr int EPT = C * R / NT;
@@ -136,7 +149,10 @@ struct Tile {
     static_assert(EPT >= 16 && EPT % 16 == 0, "tile too small");
     static_assert(NT % 64 == 0 || NT < 64, "whole waves");
 
-    __device__ static inline int lidx(int c, int r) { return STRIDED ? r * C + c : c * R + r; }
+    // contiguous tiles pad one word per 16 so that power-of-two strides spread over banks
+    static constexpr int RP = STRIDED ? R : R + R / 16;
+    static constexpr int LDS_WORDS = STRIDED ? C * R : C * RP;
+    __device__ static inline int lidx(int c, int r) { return STRIDED ? r * C + c : c * RP + r + (r >> 4); }
     template <int RAD>
     __device__ static inline void coords(int q, int &c, int &j) {
         int g = (int)threadIdx.x + q * NT;
@@ -245,7 +261,7 @@ struct KArgs {
     JobDev one;
     Tables tb;
     uint64_t S, Mprev;
-    int which;
+    int which;  // array read and written (0: A, 1: B)
 };
 
 template <class F, int LGR, int MODE>
@@ -254,6 +270,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, true>::NT)) k_strided(KArgs a) {
     using T = typename F::T;
     constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
     constexpr bool INV = (MODE == S_INV || MODE == S_INV_PARITY);
+    using Unit = typename std::conditional<C == 16, uint16_t, uint32_t>::type;
     __shared__ T lds[C * R];
 
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
@@ -279,8 +296,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, true>::NT)) k_strided(KArgs a) {
                 const uint64_t gi = base + (uint64_t)r * a.S + c;
                 T x;
                 if constexpr (MODE == S_FWD_BITS) {
-                    const Emb &e = a.which ? J.ey : J.ex;
-                    x = F::from_bit(emb_bit(e, gi, J.L));
+                    x = F::from_bit(getbit(J.eb[a.which], gi));
                 } else {
                     x = data[gi];
                 }
@@ -311,20 +327,14 @@ __global__ void __launch_bounds__((Tile<F, LGR, true>::NT)) k_strided(KArgs a) {
                 } else if constexpr (MODE == S_INV) {
                     data[gi] = x;
                 } else {
-                    // level 0 of the inverse: gi is the coefficient index. C
-                    // consecutive lanes hold C consecutive coefficients.
+                    // level 0 of the inverse: gi is the coefficient index; the C lanes
+                    // of a row hold C consecutive coefficients. Their parities go out
+                    // tile-major (unit (ct, r) at ct*R + r, contiguous per workgroup);
+                    // a transpose kernel turns that into packed natural order.
                     uint32_t b = (uint32_t)(F::canon(x) & 1u);
                     uint64_t mask = __ballot(b);
                     const int lane = (int)(threadIdx.x & 63);
-                    if (c == 0 && gi < J.out_len) {
-                        uint64_t unit = (mask >> (lane & ~(C - 1))) & ((uint64_t(1) << C) - 1);
-                        const uint64_t rem = J.out_len - gi;
-                        if (rem < (uint64_t)C) unit &= (uint64_t(1) << rem) - 1;
-                        if constexpr (C == 8)
-                            ((uint8_t *)J.pb)[gi >> 3] = (uint8_t)unit;
-                        else
-                            ((uint16_t *)J.pb)[gi >> 4] = (uint16_t)unit;
-                    }
+                    if (c == 0) ((Unit *)J.eb[0])[ct * R + r] = (Unit)(mask >> (lane & ~(C - 1)));
                 }
             }
         }
@@ -338,7 +348,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
     using Tl = Tile<F, LGR, false>;
     using T = typename F::T;
     constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
-    __shared__ T lds[C * R];
+    __shared__ T lds[Tl::LDS_WORDS];
 
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
     T *data = (T *)((MODE == C_FUSED || a.which) ? J.B : J.A);
@@ -404,7 +414,7 @@ struct SmallTile {
     static constexpr int EPT = R / NT;
     static constexpr int RF = (LG % 4) ? (1 << (LG % 4)) : 16;
     static constexpr int NSTEPS = (LG + 3) / 4;
-    __device__ static inline int lidx(int c, int r) { return r; }
+    __device__ static inline int lidx(int c, int r) { return r + (r >> 4); }
     template <int RAD>
     __device__ static inline void coords(int q, int &c, int &j) {
         c = 0;
@@ -426,7 +436,7 @@ __global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs,
     using Tl = SmallTile<LG>;
     using T = uint32_t;
     constexpr int R = Tl::R, EPT = Tl::EPT, NT = Tl::NT;
-    __shared__ T lds[R];
+    __shared__ T lds[R + R / 16];
     __shared__ uint32_t red[2];
 
     const JobDev &J = jobs ? jobs[blockIdx.x] : one;
@@ -465,7 +475,7 @@ __global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs,
         int c, j;
         Tl::template coords<RADI>(q, c, j);
 #pragma unroll
-        for (int t = 0; t < RADI; ++t) lds[j + t * (R / RADI)] = vb[q * RADI + t];
+        for (int t = 0; t < RADI; ++t) lds[Tl::lidx(0, j + t * (R / RADI))] = vb[q * RADI + t];
     }
     // degenerate check (Dodis): any one bit and any zero bit among x_0..x_{n-1}
     if (threadIdx.x < 2) red[threadIdx.x] = 0;
@@ -492,8 +502,8 @@ __global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs,
             for (int b = 0; b < 64; ++b) {
                 uint64_t i = w * 64 + b;
                 if (i >= J.m) break;
-                uint32_t bit = lds[i] & 1u;
-                if (J.nfold) bit ^= lds[i + J.nfold] & 1u;
+                uint32_t bit = lds[Tl::lidx(0, (int)i)] & 1u;
+                if (J.nfold) bit ^= lds[Tl::lidx(0, (int)(i + J.nfold))] & 1u;
                 word |= (uint64_t)bit << b;
             }
         }
@@ -503,6 +513,78 @@ __global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs,
 }
 
 #if NTT_HAS(4)
+// ------------------------------------------------------------------ embedding of the packed inputs
+
+// cnt (<= 64) bits of b starting at bit `start`, as the low bits of a word
+__host__ __device__ inline uint64_t bits_at(const uint64_t *b, uint64_t start, int cnt) {
+    const uint64_t q = start >> 6;
+    const int o = (int)(start & 63);
+    uint64_t w = b[q] >> o;
+    if (o && o + cnt > 64) w |= b[q + 1] << (64 - o);
+    return cnt == 64 ? w : (w & ((uint64_t(1) << cnt) - 1));
+}
+
+// Word w of the L-bit coefficient string of embedding e: bit t is emb_bit(e, 64w + t),
+// assembled from runs of consecutive source bits.
+__host__ __device__ inline uint64_t embed_word(const Emb &e, uint64_t L, uint64_t w) {
+    const uint64_t i0 = w * 64;
+    uint64_t out = 0;
+    if (e.mode == EMB_PREFIX) {
+        if (i0 >= e.len) return 0;
+        const int cnt = (int)umin64(64, e.len - i0);
+        return bits_at(e.bits, i0, cnt);
+    }
+    if (e.mode == EMB_SEED) {
+        int pos = 0;
+        while (pos < 64) {
+            uint64_t k = i0 + pos + e.a;
+            if (k >= L) k -= L;
+            if (k >= e.N) {  // zeros until k wraps at L
+                pos += (int)umin64(64 - pos, L - k);
+                continue;
+            }
+            uint64_t src = k + e.rot;
+            if (src >= e.N) src -= e.N;
+            const int run = (int)umin64(64 - pos, umin64(e.N - k, e.N - src));
+            out |= bits_at(e.bits, src, run) << pos;
+            pos += run;
+        }
+        return out;
+    }
+    // REVERSE: position i < N holds b'_{(N - i) mod N}, b'_j = j < len ? b_j : 0
+    for (int t = 0; t < 64;) {
+        const uint64_t i = i0 + t;
+        if (i >= e.N) break;
+        if (i == 0) {
+            out |= (uint64_t)(e.len ? getbit(e.bits, 0) : 0u);
+            ++t;
+            continue;
+        }
+        // positions i .. i+run-1 read j = N-i down to N-i-run+1 (all >= 1)
+        const uint64_t j = e.N - i;
+        int run = (int)umin64(64 - t, umin64(j, e.N - i));
+        if (j >= e.len) {  // sources beyond len are zero; skip to j = len - 1
+            const uint64_t skip = j - e.len + 1;
+            t += (int)umin64(skip, (uint64_t)(64 - t));
+            continue;
+        }
+        const uint64_t jlo = j - run + 1;
+        const uint64_t rev = __builtin_bitreverse64(bits_at(e.bits, jlo, run)) >> (64 - run);
+        out |= rev << t;
+        t += run;
+    }
+    return out;
+}
+
+__global__ void __launch_bounds__(256) k_embed(const JobDev *jobs, JobDev one) {
+    const JobDev &J = jobs ? jobs[blockIdx.y] : one;
+    const uint64_t nw = J.L >> 6;
+    const int which = blockIdx.z;
+    const Emb &e = which ? J.ey : J.ex;
+    for (uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * 256)
+        J.eb[which][w] = embed_word(e, J.L, w);
+}
+
 // ------------------------------------------------------------------ pack, degenerate check
 
 __global__ void __launch_bounds__(256) k_pack(const JobDev *jobs, JobDev one) {
@@ -522,6 +604,37 @@ __global__ void __launch_bounds__(256) k_pack(const JobDev *jobs, JobDev one) {
         J.z[w] = degen ? 0ull : word;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && J.status) *J.status = degen ? -3 : 0;
+}
+
+// Tile-major parity units (unit u of row r at u*R + r, C bits each, in J.eb[0]) to
+// packed natural order in J.pb (bit r*S + u*C + c). 64 x 64 units per workgroup
+// through LDS, coalesced on both sides.
+template <int C>
+__global__ void __launch_bounds__(256) k_ptrans(const JobDev *jobs, JobDev one, uint64_t R, uint64_t S) {
+    using Unit = typename std::conditional<C == 16, uint16_t, uint32_t>::type;
+    constexpr int UPW = 64 / C;  // units per word
+    __shared__ Unit tl[64][65];
+    const JobDev &J = jobs ? jobs[blockIdx.z] : one;
+    const Unit *U = (const Unit *)J.eb[0];
+    const uint64_t units = S / C;
+    const uint64_t r0 = (uint64_t)blockIdx.x * 64, u0 = (uint64_t)blockIdx.y * 64;
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+        const int uu = idx >> 6, rr = idx & 63;
+        const uint64_t u = u0 + uu, r = r0 + rr;
+        tl[rr][uu] = (u < units && r < R) ? U[u * R + r] : (Unit)0;
+    }
+    __syncthreads();
+    constexpr int WPR = 64 / UPW;  // words per tile row
+    for (int idx = threadIdx.x; idx < 64 * WPR; idx += 256) {
+        const int rr = idx / WPR, wk = idx % WPR;
+        const uint64_t r = r0 + rr, u = u0 + (uint64_t)wk * UPW;
+        if (r < R && u < units) {
+            uint64_t word = 0;
+#pragma unroll
+            for (int k = 0; k < UPW; ++k) word |= (uint64_t)tl[rr][wk * UPW + k] << (k * C);
+            J.pb[r * (S / 64) + u / UPW] = word;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_degen(const JobDev *jobs, JobDev one) {
@@ -585,7 +698,7 @@ static hipError_t contig_one(const PassLaunch &p, const KArgs &ka, hipStream_t s
     return hipGetLastError();
 }
 
-constexpr int BB_STRIDED_MAX = 11, BB_CONTIG_MAX = 14, GL_STRIDED_MAX = 10, GL_CONTIG_MAX = 12;
+constexpr int BB_STRIDED_MAX = 10, BB_CONTIG_MAX = 14, GL_STRIDED_MAX = 10, GL_CONTIG_MAX = 13;
 constexpr int SMALL_MAX = 14;
 
 hipError_t launch_strided_bb(const PassLaunch &p, const Tables &t, hipStream_t s);
@@ -601,7 +714,6 @@ hipError_t launch_strided_bb(const PassLaunch &p, const Tables &t, hipStream_t s
         case 8: return strided_one<FBB, 8>(p, ka, s);
         case 9: return strided_one<FBB, 9>(p, ka, s);
         case 10: return strided_one<FBB, 10>(p, ka, s);
-        case 11: return strided_one<FBB, 11>(p, ka, s);
     }
     return hipErrorInvalidValue;
 }
@@ -647,6 +759,7 @@ hipError_t launch_contig_gl(const PassLaunch &p, const Tables &t, hipStream_t s)
         case 10: return contig_one<FGL, 10>(p, ka, s);
         case 11: return contig_one<FGL, 11>(p, ka, s);
         case 12: return contig_one<FGL, 12>(p, ka, s);
+        case 13: return contig_one<FGL, 13>(p, ka, s);
     }
     return hipErrorInvalidValue;
 }
@@ -661,7 +774,7 @@ template <class F>
 static Geometry geo_s(int lgr) {
     switch (lgr) {
 #define G(L) case L: return Geometry{Tile<F, L, true>::C, Tile<F, L, true>::NT};
-        G(7) G(8) G(9) G(10) G(11)
+        G(7) G(8) G(9) G(10)
 #undef G
     }
     return Geometry{0, 0};
@@ -717,6 +830,30 @@ hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, c
     unsigned gx = (unsigned)((max_words + 255) / 256);
     if (gx == 0) gx = 1;
     hipLaunchKernelGGL(k_pack, dim3(gx, njobs), dim3(256), 0, s, jobs, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_embed(uint32_t njobs, uint64_t max_L, const JobDev *jobs, const JobDev *one, hipStream_t s) {
+    JobDev o;
+    if (one) o = *one;
+    else std::memset(&o, 0, sizeof(o));
+    uint64_t words = max_L >> 6;
+    unsigned gx = (unsigned)umin64((words + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_embed, dim3(gx, njobs, 2), dim3(256), 0, s, jobs, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint32_t njobs, const JobDev *jobs, const JobDev *one,
+                         hipStream_t s) {
+    JobDev o;
+    if (one) o = *one;
+    else std::memset(&o, 0, sizeof(o));
+    const int C = field == FIELD_BB ? 32 : 16;
+    dim3 grid((unsigned)((R + 63) / 64), (unsigned)((S / C + 63) / 64), njobs);
+    if (C == 16)
+        hipLaunchKernelGGL(k_ptrans<16>, grid, dim3(256), 0, s, jobs, o, R, S);
+    else
+        hipLaunchKernelGGL(k_ptrans<32>, grid, dim3(256), 0, s, jobs, o, R, S);
     return hipGetLastError();
 }
 
