@@ -62,6 +62,11 @@ extern "C" {
 #define EXT_SEED_LINEAR 1u
 /* Wait for the stream and return the device status. */
 #define EXT_SYNC 2u
+/* extract_batch only: capture the batch's launch sequence into a HIP graph on
+ * first use of a batch signature (the multiset of transform sizes) and replay it
+ * afterwards. Worth it when the same signature repeats; without the flag the
+ * grouped launches are enqueued directly. */
+#define EXT_GRAPH 4u
 
 typedef struct ext_ctx ext_ctx;
 
@@ -121,14 +126,16 @@ typedef struct ext_job {
 
 /* Run many independent extractions (the paper's many privacy-amplification
  * blocks, section "Cryptomite for privacy amplification in QKD") as a few
- * grouped launches: jobs are grouped by transform size; small sizes run one
- * workgroup per job in a single launch, larger ones as batched multi-pass
- * launches; the launch sequence for a batch signature is captured once into
- * a HIP graph and replayed. `jobs` is a host array of `count` entries.
- * Each job is validated on the host first and gets job.err; invalid jobs are
- * skipped (their z untouched). Returns EXT_OK if every job was enqueued, the
- * first failing job's code if some were skipped, or a context-level error
- * (EXT_ENOMEM, EXT_EDEVICE) with nothing enqueued. flags: 0 or EXT_SYNC. */
+ * grouped launches: jobs are grouped by transform size; all single-workgroup
+ * sizes (transform length <= 2^14) run in one persistent launch that takes
+ * jobs from a work counter, larger sizes as batched multi-pass launches, one
+ * set per size class. With EXT_GRAPH the launch sequence of a batch signature
+ * is captured once into a HIP graph and replayed. `jobs` is a host array of
+ * `count` entries. Each job is validated on the host first and gets job.err;
+ * invalid jobs are skipped (their z untouched). Returns EXT_OK if every job
+ * was enqueued, the first failing job's code if some were skipped, or a
+ * context-level error (EXT_ENOMEM, EXT_EDEVICE) with nothing enqueued.
+ * flags: EXT_SYNC, EXT_GRAPH. */
 int extract_batch(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t flags, void *stream);
 
 /* The same jobs, one extraction call sequence per job (no grouping, no

@@ -132,9 +132,13 @@ class Context:
             raise ExtError(rc, "extract_" + kind)
         return z if check else (rc, z)
 
-    def batch(self, jobs, sync: bool = False, stream=None, unbatched: bool = False):
+    def workspace_bytes(self, kind: str, n: int, m: int) -> int:
+        return int(self._lib.ext_workspace_bytes(KINDS[kind], int(n), int(m)))
+
+    def batch(self, jobs, sync: bool = False, stream=None, unbatched: bool = False, graph: bool = False):
         """jobs: list of dicts with kind, n, m, x, y, z[, seed_order, status]. Returns the
-        library's return code and the per-job host validation codes."""
+        library's return code and the per-job host validation codes. graph=True captures
+        the launch sequence of this batch signature into a HIP graph and replays it."""
         arr = (ExtJob * len(jobs))()
         for i, j in enumerate(jobs):
             arr[i].kind = KINDS[j["kind"]]
@@ -147,7 +151,8 @@ class Context:
             st = j.get("status")
             arr[i].status = st.data_ptr() if st is not None else None
         fn = self._lib.extract_batch_unbatched if unbatched else self._lib.extract_batch
-        rc = fn(self.handle, arr, len(jobs), EXT_SYNC if sync else 0, _stream_handle(stream))
+        flags = (EXT_SYNC if sync else 0) | (_lib.EXT_GRAPH if (graph and not unbatched) else 0)
+        rc = fn(self.handle, arr, len(jobs), flags, _stream_handle(stream))
         return rc, [arr[i].err for i in range(len(jobs))]
 
 

@@ -22,6 +22,7 @@ EXT_EDEVICE = -6
 EXT_SEED_PAPER = 0
 EXT_SEED_LINEAR = 1
 EXT_SYNC = 2
+EXT_GRAPH = 4
 
 EXT_KIND_TOEPLITZ = 0
 EXT_KIND_CIRCULANT = 1

@@ -667,6 +667,10 @@ int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint6
 
 }  // namespace
 
+namespace {
+void pinned_release_all(ext_ctx *c);
+}
+
 // ================================================================== C-ABI
 
 extern "C" {
@@ -796,6 +800,7 @@ void ext_destroy(ext_ctx *c) {
         for (int k = 0; k < 3; ++k)
             if (c->tb_mem[f][k]) hipFree(c->tb_mem[f][k]);
     for (auto p : c->pinned_status) hipHostFree(p);
+    pinned_release_all(c);
     for (auto &mk : c->marks) {
         hipEventDestroy(mk.a);
         hipEventDestroy(mk.b);
@@ -917,16 +922,198 @@ std::string plan_key(const Plan &p) {
     return b;
 }
 
+// Launch layout of a batch: single-workgroup jobs first (sorted by size, one
+// persistent launch), then chunks of one multi-pass size class each. A chunk's
+// jobs get consecutive workspaces; chunks run one after another in stream
+// order and share one workspace region, capped so that a chunk fits it.
+struct BatchLayout {
+    std::vector<const Member *> order;
+    SmallClasses cls{};
+    size_t n_small = 0;
+    struct Chunk {
+        Plan plan;
+        size_t first_desc, n;
+        uint64_t max_m;
+        bool any_degen;
+        size_t ws_each;
+    };
+    std::vector<Chunk> chunks;
+    size_t max_ws = 0;
+    std::string sig;
+};
+
+void layout_batch(ext_ctx *c, const std::vector<Member> &members, BatchLayout &bl) {
+    std::vector<const Member *> small;
+    std::map<std::string, std::vector<const Member *>> large;
+    for (auto &mb : members) {
+        if (mb.plan.small)
+            small.push_back(&mb);
+        else
+            large[plan_key(mb.plan)].push_back(&mb);
+    }
+    std::stable_sort(small.begin(), small.end(),
+                     [](const Member *a, const Member *b) { return a->plan.lg > b->plan.lg; });
+    bl.n_small = small.size();
+    uint32_t item = 0;
+    for (size_t i = 0; i < small.size();) {
+        const int lg = small[i]->plan.lg;
+        size_t j = i;
+        while (j < small.size() && small[j]->plan.lg == lg) ++j;
+        const int k = bl.cls.n++;
+        bl.cls.lg[k] = lg;
+        bl.cls.first_job[k] = (uint32_t)i;
+        bl.cls.njobs[k] = (uint32_t)(j - i);
+        bl.cls.first_item[k] = item;
+        const size_t jpw = size_t(1) << (14 - lg);
+        item += (uint32_t)((j - i + jpw - 1) / jpw);
+        char b[32];
+        snprintf(b, sizeof b, "s%d#%zu|", lg, j - i);
+        bl.sig += b;
+        i = j;
+    }
+    bl.cls.total_items = item;
+    bl.order = small;
+    const size_t cap = std::max<size_t>(size_t(1) << 30, std::min<size_t>(c->budget / 4, size_t(16) << 30));
+    for (auto &kv : large) {
+        const Plan &p = kv.second.front()->plan;
+        const size_t each = workspace_layout(p).total;
+        size_t per_chunk = std::max<size_t>(1, cap / each);
+        per_chunk = std::min<size_t>(per_chunk, 65535);
+        for (size_t s0 = 0; s0 < kv.second.size(); s0 += per_chunk) {
+            BatchLayout::Chunk ch;
+            ch.plan = p;
+            ch.first_desc = bl.order.size();
+            ch.n = std::min(per_chunk, kv.second.size() - s0);
+            ch.max_m = 0;
+            ch.any_degen = false;
+            ch.ws_each = each;
+            for (size_t k = 0; k < ch.n; ++k) {
+                const Member *mb = kv.second[s0 + k];
+                bl.order.push_back(mb);
+                ch.max_m = std::max(ch.max_m, mb->shape.m);
+                ch.any_degen |= mb->shape.kind == EXT_KIND_DODIS;
+            }
+            bl.max_ws = std::max(bl.max_ws, each * ch.n);
+            bl.chunks.push_back(ch);
+            char b[96];
+            snprintf(b, sizeof b, "%s#%zu:%llu:%d|", kv.first.c_str(), ch.n, (unsigned long long)ch.max_m,
+                     ch.any_degen ? 1 : 0);
+            bl.sig += b;
+        }
+    }
+}
+
+void fill_descs(const BatchLayout &bl, const ext_job *jobs, char *ws, JobDev *out) {
+    for (size_t i = 0; i < bl.n_small; ++i) {
+        const Member &mb = *bl.order[i];
+        const ext_job &j = jobs[mb.job];
+        out[i] = make_jobdev(mb.shape, mb.plan, j.x, j.y, j.z, j.status, j.flags & EXT_SEED_LINEAR, nullptr);
+    }
+    for (auto &ch : bl.chunks)
+        for (size_t k = 0; k < ch.n; ++k) {
+            const Member &mb = *bl.order[ch.first_desc + k];
+            const ext_job &j = jobs[mb.job];
+            out[ch.first_desc + k] =
+                make_jobdev(mb.shape, mb.plan, j.x, j.y, j.z, j.status, j.flags & EXT_SEED_LINEAR, ws + k * ch.ws_each);
+        }
+}
+
+hipError_t enqueue_batch(ext_ctx *c, const BatchLayout &bl, JobDev *desc_dev, uint32_t *counter, hipStream_t s,
+                         bool capturing) {
+    hipError_t e = hipSuccess;
+    if (bl.cls.total_items) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) cus = 256;
+        const unsigned wgs = std::min<unsigned>(bl.cls.total_items, (unsigned)(2 * cus));
+        Tracer tr(c, s, capturing);
+        tr.begin();
+        e = launch_small_batch(bl.cls, desc_dev, counter, wgs, c->tb[FIELD_BB], s);
+        tr.end("small_persist");
+        if (e != hipSuccess) return e;
+    }
+    for (auto &ch : bl.chunks) {
+        e = enqueue(c, ch.plan, (uint32_t)ch.n, desc_dev + ch.first_desc, nullptr, ch.max_m, ch.any_degen, s,
+                    capturing);
+        if (e != hipSuccess) return e;
+    }
+    return e;
+}
+
+// Pinned staging for descriptor uploads, recycled once the copy that read it is done.
+struct Pinned {
+    char *ptr;
+    size_t size;
+    hipEvent_t ev;
+};
+
+}  // namespace
+
+struct ext_pinned_ring {
+    std::vector<Pinned> items;
+};
+
+namespace {
+std::mutex g_ring_mu;
+std::map<ext_ctx *, ext_pinned_ring> g_rings;
+
+char *pinned_take(ext_ctx *c, size_t bytes, Pinned &out) {
+    std::lock_guard<std::mutex> g(g_ring_mu);
+    auto &ring = g_rings[c].items;
+    for (size_t i = 0; i < ring.size(); ++i) {
+        if (ring[i].size >= bytes && hipEventQuery(ring[i].ev) == hipSuccess) {
+            out = ring[i];
+            ring.erase(ring.begin() + i);
+            return out.ptr;
+        }
+    }
+    out.size = std::max<size_t>(bytes, 4096);
+    if (hipHostMalloc((void **)&out.ptr, out.size, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&out.ev, hipEventDisableTiming) != hipSuccess) {
+        hipHostFree(out.ptr);
+        return nullptr;
+    }
+    return out.ptr;
+}
+
+void pinned_give(ext_ctx *c, Pinned &p, hipStream_t s) {
+    hipEventRecord(p.ev, s);
+    std::lock_guard<std::mutex> g(g_ring_mu);
+    auto &ring = g_rings[c].items;
+    ring.push_back(p);
+    if (ring.size() > 64) {  // keep the ring bounded: drop the oldest idle buffer
+        for (size_t i = 0; i < ring.size(); ++i)
+            if (hipEventQuery(ring[i].ev) == hipSuccess) {
+                hipEventDestroy(ring[i].ev);
+                hipHostFree(ring[i].ptr);
+                ring.erase(ring.begin() + i);
+                break;
+            }
+    }
+}
+
+void pinned_release_all(ext_ctx *c) {
+    std::lock_guard<std::mutex> g(g_ring_mu);
+    auto it = g_rings.find(c);
+    if (it == g_rings.end()) return;
+    for (auto &p : it->second.items) {
+        hipEventDestroy(p.ev);
+        hipHostFree(p.ptr);
+    }
+    g_rings.erase(it);
+}
+
+constexpr size_t GRAPH_CACHE_MAX = 32;
+
 }  // namespace
 
 extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t flags, void *stream_) {
     if (!c || (!jobs && count)) return EXT_EINVAL;
-    if (flags & ~EXT_SYNC) return EXT_EINVAL;
+    if (flags & ~(EXT_SYNC | EXT_GRAPH)) return EXT_EINVAL;
     hipStream_t stream = (hipStream_t)stream_;
     if (hipSetDevice(c->device) != hipSuccess) return EXT_EDEVICE;
     int first = EXT_OK;
-    // validate, plan, group
-    std::map<std::string, std::vector<Member>> groups;
+    std::vector<Member> members;
+    members.reserve(count);
     for (size_t i = 0; i < count; ++i) {
         ext_job &j = jobs[i];
         Member mb;
@@ -941,106 +1128,83 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
             if (first == EXT_OK) first = rc;
             continue;
         }
-        groups[plan_key(mb.plan)].push_back(mb);
+        members.push_back(mb);
     }
-    if (groups.empty()) return first;
-    // Chunks: groups are split so that one chunk's workspace stays under a cap;
-    // chunks run one after another and share one workspace lease.
-    const size_t cap = std::max<size_t>(size_t(1) << 30, std::min<size_t>(c->budget / 4, size_t(16) << 30));
-    struct Chunk {
-        Plan plan;
-        size_t first_desc, n;
-        uint64_t max_m;
-        bool any_degen;
-        size_t ws_each;
-    };
-    std::vector<Chunk> chunks;
-    std::vector<const Member *> order;
-    size_t max_ws = 0;
-    std::string sig;
-    for (auto &kv : groups) {
-        const Plan &p = kv.second.front().plan;
-        const size_t each = workspace_layout(p).total;
-        size_t per_chunk = each ? std::max<size_t>(1, cap / each) : kv.second.size();
-        per_chunk = std::min<size_t>(per_chunk, 65535);
-        for (size_t s0 = 0; s0 < kv.second.size(); s0 += per_chunk) {
-            Chunk ch;
-            ch.plan = p;
-            ch.first_desc = order.size();
-            ch.n = std::min(per_chunk, kv.second.size() - s0);
-            ch.max_m = 0;
-            ch.any_degen = false;
-            ch.ws_each = each;
-            for (size_t k = 0; k < ch.n; ++k) {
-                const Member &mb = kv.second[s0 + k];
-                order.push_back(&mb);
-                ch.max_m = std::max(ch.max_m, mb.shape.m);
-                ch.any_degen |= mb.shape.kind == EXT_KIND_DODIS;
+    if (members.empty()) return first;
+    BatchLayout bl;
+    layout_batch(c, members, bl);
+    const size_t ndesc = bl.order.size();
+    const size_t desc_bytes = align256(ndesc * sizeof(JobDev));
+    hipError_t e = hipSuccess;
+    if (flags & EXT_GRAPH) {
+        Lease lease;
+        int rc = pool_acquire(c, bl.max_ws, stream, lease);
+        if (rc != EXT_OK) return rc;
+        ext_ctx::GraphEntry *ge;
+        {
+            std::lock_guard<std::mutex> g(c->mu);
+            if (c->graphs.size() >= GRAPH_CACHE_MAX && !c->graphs.count(bl.sig)) {
+                // bounded cache: evict an entry whose last replay is done
+                for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
+                    if (!it->second.ever || hipEventQuery(it->second.done) == hipSuccess) {
+                        if (it->second.exec) hipGraphExecDestroy(it->second.exec);
+                        if (it->second.desc_dev) hipFree(it->second.desc_dev);
+                        if (it->second.desc_host) hipHostFree(it->second.desc_host);
+                        if (it->second.done) hipEventDestroy(it->second.done);
+                        c->graphs.erase(it);
+                        break;
+                    }
+                }
             }
-            max_ws = std::max(max_ws, each * ch.n);
-            chunks.push_back(ch);
-            char b[96];
-            snprintf(b, sizeof b, "%s#%zu:%llu:%d|", kv.first.c_str(), ch.n, (unsigned long long)ch.max_m,
-                     ch.any_degen ? 1 : 0);
-            sig += b;
+            ge = &c->graphs[bl.sig];
         }
-    }
-    Lease lease;
-    int rc = pool_acquire(c, max_ws, stream, lease);
-    if (rc != EXT_OK) return rc;
-    // graph cache entry for this batch signature
-    ext_ctx::GraphEntry *ge;
-    {
-        std::lock_guard<std::mutex> g(c->mu);
-        ge = &c->graphs[sig];
-    }
-    if (!ge->desc_dev) {
-        ge->ndesc = order.size();
-        if (hipMalloc((void **)&ge->desc_dev, ge->ndesc * sizeof(JobDev)) != hipSuccess ||
-            hipHostMalloc((void **)&ge->desc_host, ge->ndesc * sizeof(JobDev), hipHostMallocDefault) != hipSuccess ||
-            hipEventCreateWithFlags(&ge->done, hipEventDisableTiming) != hipSuccess) {
-            pool_release(c, lease, stream);
-            return EXT_EDEVICE;
+        if (!ge->desc_dev) {
+            ge->ndesc = ndesc;
+            if (hipMalloc((void **)&ge->desc_dev, desc_bytes + 256) != hipSuccess ||
+                hipHostMalloc((void **)&ge->desc_host, desc_bytes, hipHostMallocDefault) != hipSuccess ||
+                hipEventCreateWithFlags(&ge->done, hipEventDisableTiming) != hipSuccess) {
+                pool_release(c, lease, stream);
+                return EXT_EDEVICE;
+            }
         }
-    }
-    // the pinned descriptor staging of this signature may still be read by the previous replay's copy
-    if (ge->ever) hipEventSynchronize(ge->done);
-    for (auto &ch : chunks) {
-        for (size_t k = 0; k < ch.n; ++k) {
-            const Member &mb = *order[ch.first_desc + k];
-            const ext_job &j = jobs[mb.job];
-            char *ws = ch.ws_each ? lease.ptr + k * ch.ws_each : nullptr;
-            ge->desc_host[ch.first_desc + k] =
-                make_jobdev(mb.shape, mb.plan, j.x, j.y, j.z, j.status, j.flags & EXT_SEED_LINEAR, ws);
+        uint32_t *counter = (uint32_t *)((char *)ge->desc_dev + desc_bytes);
+        // the staging of this signature may still be read by the previous replay's copy
+        if (ge->ever) hipEventSynchronize(ge->done);
+        fill_descs(bl, jobs, lease.ptr, ge->desc_host);
+        e = hipMemcpyAsync(ge->desc_dev, ge->desc_host, ndesc * sizeof(JobDev), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && !ge->exec) {
+            hipGraph_t graph = nullptr;
+            e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) e = enqueue_batch(c, bl, ge->desc_dev, counter, c->capture_stream, true);
+            hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&ge->exec, graph, nullptr, nullptr, 0);
+            if (graph) hipGraphDestroy(graph);
+            if (e != hipSuccess) ge->exec = nullptr;
         }
-    }
-    if (hipMemcpyAsync(ge->desc_dev, ge->desc_host, ge->ndesc * sizeof(JobDev), hipMemcpyHostToDevice, stream) !=
-        hipSuccess) {
+        if (e == hipSuccess) e = hipGraphLaunch(ge->exec, stream);
+        hipEventRecord(ge->done, stream);
+        ge->ever = true;
         pool_release(c, lease, stream);
-        return EXT_EDEVICE;
-    }
-    if (!ge->exec) {
-        hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
-        for (auto &ch : chunks) {
-            if (e != hipSuccess) break;
-            e = enqueue(c, ch.plan, (uint32_t)ch.n, ge->desc_dev + ch.first_desc, nullptr, ch.max_m, ch.any_degen,
-                        c->capture_stream, true);
-        }
-        hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
-        if (e == hipSuccess) e = e2;
-        if (e == hipSuccess) e = hipGraphInstantiate(&ge->exec, graph, nullptr, nullptr, 0);
-        if (graph) hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            ge->exec = nullptr;
+    } else {
+        // descriptors and the work counter live at the front of the leased workspace
+        Lease lease;
+        int rc = pool_acquire(c, desc_bytes + 256 + bl.max_ws, stream, lease);
+        if (rc != EXT_OK) return rc;
+        Pinned pin;
+        JobDev *host = (JobDev *)pinned_take(c, ndesc * sizeof(JobDev), pin);
+        if (!host) {
             pool_release(c, lease, stream);
             return EXT_EDEVICE;
         }
+        JobDev *desc_dev = (JobDev *)lease.ptr;
+        uint32_t *counter = (uint32_t *)(lease.ptr + desc_bytes);
+        fill_descs(bl, jobs, lease.ptr + desc_bytes + 256, host);
+        e = hipMemcpyAsync(desc_dev, host, ndesc * sizeof(JobDev), hipMemcpyHostToDevice, stream);
+        pinned_give(c, pin, stream);
+        if (e == hipSuccess) e = enqueue_batch(c, bl, desc_dev, counter, stream, false);
+        pool_release(c, lease, stream);
     }
-    hipError_t e = hipGraphLaunch(ge->exec, stream);
-    hipEventRecord(ge->done, stream);
-    ge->ever = true;
-    pool_release(c, lease, stream);
     if (e != hipSuccess) return EXT_EDEVICE;
     if ((flags & EXT_SYNC) && hipStreamSynchronize(stream) != hipSuccess) return EXT_EDEVICE;
     return first;

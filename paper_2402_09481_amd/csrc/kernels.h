@@ -90,6 +90,18 @@ hipError_t launch_contig(const PassLaunch &p, const Tables &t, hipStream_t s);
 // Whole extraction in one workgroup (field FBB, L = 2^lg <= 2^14).
 hipError_t launch_small(int lg, uint32_t njobs, const JobDev *jobs, const JobDev *one, const Tables &t,
                         hipStream_t s);
+// Size classes of a persistent small-job launch (jobs sorted by class).
+struct SmallClasses {
+    int n;                    // number of classes (<= 9: lengths 2^6 .. 2^14)
+    int lg[9];
+    uint32_t first_job[9];    // index of the class's first job in the descriptor array
+    uint32_t njobs[9];
+    uint32_t first_item[9];   // work items of earlier classes
+    uint32_t total_items;
+};
+// All single-workgroup jobs of a batch in one persistent launch (after zeroing *counter).
+hipError_t launch_small_batch(const SmallClasses &cls, const JobDev *jobs, uint32_t *counter, unsigned workgroups,
+                              const Tables &t, hipStream_t s);
 // Packed parity -> z (fold, mask, degenerate check result, status).
 hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, const JobDev *one, hipStream_t s);
 // Lay out both inputs as L-bit coefficient strings (eb[0], eb[1]).

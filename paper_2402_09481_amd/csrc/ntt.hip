@@ -404,21 +404,26 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
     }
 }
 
-// ------------------------------------------------------------------ small: one job per workgroup
+// ------------------------------------------------------------------ small: whole job in one thread group
 
+// A job of length L = 2^LG is done by a group of NT = L/16 threads (16 values each)
+// with L (+ padding) words of LDS. Groups are NT-aligned blocks of a workgroup,
+// so a thread's index within its group is threadIdx.x & (NT - 1).
 template <int LG>
 struct SmallTile {
     static constexpr int R = 1 << LG;
     static constexpr int C = 1;
-    static constexpr int NT = R / 16;  // 16 values per thread (a partial wave for L < 2^10)
+    static constexpr int NT = R / 16;  // a partial wave for L < 2^10
     static constexpr int EPT = R / NT;
     static constexpr int RF = (LG % 4) ? (1 << (LG % 4)) : 16;
     static constexpr int NSTEPS = (LG + 3) / 4;
+    static constexpr int LDS_WORDS = R + R / 16;
+    __device__ static inline int lid() { return (int)(threadIdx.x & (NT - 1)); }
     __device__ static inline int lidx(int c, int r) { return r + (r >> 4); }
     template <int RAD>
     __device__ static inline void coords(int q, int &c, int &j) {
         c = 0;
-        j = (int)threadIdx.x + q * NT;
+        j = lid() + q * NT;
     }
     __host__ __device__ static constexpr int radix(int s, bool inv) {
         return inv ? (s == NSTEPS - 1 ? RF : 16) : (s == 0 ? RF : 16);
@@ -430,21 +435,21 @@ struct SmallTile {
     }
 };
 
+// The whole extraction of job J by one thread group: both forward transforms,
+// the pointwise product, the inverse, parity, fold, pack, and the Dodis
+// degenerate-input check. Every thread of the workgroup must call this (it
+// contains workgroup barriers); `write` = false runs the arithmetic without
+// writing any output (idle groups of a persistent workgroup).
 template <int LG>
-__global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs, JobDev one, Tables tb) {
+__device__ inline void small_body(const JobDev &J, bool write, uint32_t *lds, uint32_t *red, const Tables &tb) {
     using F = FBB;
     using Tl = SmallTile<LG>;
     using T = uint32_t;
     constexpr int R = Tl::R, EPT = Tl::EPT, NT = Tl::NT;
-    __shared__ T lds[R + R / 16];
-    __shared__ uint32_t red[2];
-
-    const JobDev &J = jobs ? jobs[blockIdx.x] : one;
     constexpr int RAD0 = Ends<Tl, false>::RAD_FIRST;
-    constexpr int RADL = Ends<Tl, false>::RAD_LAST;
+    const int lt = Tl::lid();
 
     T va[EPT], vb[EPT];
-    // input transform
 #pragma unroll
     for (int q = 0; q < EPT / RAD0; ++q) {
         int c, j;
@@ -454,7 +459,6 @@ __global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs,
     }
     run_steps_from<F, Tl, false, 0>(va, lds, tb);
     __syncthreads();
-    // seed transform
 #pragma unroll
     for (int q = 0; q < EPT / RAD0; ++q) {
         int c, j;
@@ -477,13 +481,12 @@ __global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs,
 #pragma unroll
         for (int t = 0; t < RADI; ++t) lds[Tl::lidx(0, j + t * (R / RADI))] = vb[q * RADI + t];
     }
-    // degenerate check (Dodis): any one bit and any zero bit among x_0..x_{n-1}
-    if (threadIdx.x < 2) red[threadIdx.x] = 0;
+    if (lt < 2) red[lt] = 0;
     __syncthreads();
     if (J.degen_n) {
         const uint64_t nw = (J.degen_n + 63) >> 6;
         uint32_t one_ = 0, zero_ = 0;
-        for (uint64_t w = threadIdx.x; w < nw; w += NT) {
+        for (uint64_t w = lt; w < nw; w += NT) {
             uint64_t x = J.ex.bits[w];
             uint64_t mk = (w + 1 < nw || (J.degen_n & 63) == 0) ? ~0ull : ((1ull << (J.degen_n & 63)) - 1);
             one_ |= (x & mk) != 0;
@@ -494,22 +497,32 @@ __global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs,
     }
     __syncthreads();
     const bool degen = J.degen_n && (red[0] == 0 || red[1] == 0);
-    // parity, fold, pack: thread per output word
-    const uint64_t nwm = (J.m + 63) >> 6;
-    for (uint64_t w = threadIdx.x; w < nwm; w += NT) {
-        uint64_t word = 0;
-        if (!degen) {
-            for (int b = 0; b < 64; ++b) {
-                uint64_t i = w * 64 + b;
-                if (i >= J.m) break;
-                uint32_t bit = lds[Tl::lidx(0, (int)i)] & 1u;
-                if (J.nfold) bit ^= lds[Tl::lidx(0, (int)(i + J.nfold))] & 1u;
-                word |= (uint64_t)bit << b;
+    if (write) {
+        const uint64_t nwm = (J.m + 63) >> 6;
+        for (uint64_t w = lt; w < nwm; w += NT) {
+            uint64_t word = 0;
+            if (!degen) {
+                for (int b = 0; b < 64; ++b) {
+                    uint64_t i = w * 64 + b;
+                    if (i >= J.m) break;
+                    uint32_t bit = lds[Tl::lidx(0, (int)i)] & 1u;
+                    if (J.nfold) bit ^= lds[Tl::lidx(0, (int)(i + J.nfold))] & 1u;
+                    word |= (uint64_t)bit << b;
+                }
             }
+            J.z[w] = word;
         }
-        J.z[w] = word;
+        if (lt == 0 && J.status) *J.status = degen ? -3 : 0;
     }
-    if (threadIdx.x == 0 && J.status) *J.status = degen ? -3 : 0;
+}
+
+// One job per workgroup.
+template <int LG>
+__global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs, JobDev one, Tables tb) {
+    __shared__ uint32_t lds[SmallTile<LG>::LDS_WORDS];
+    __shared__ uint32_t red[2];
+    const JobDev &J = jobs ? jobs[blockIdx.x] : one;
+    small_body<LG>(J, true, lds, red, tb);
 }
 
 #if NTT_HAS(4)
@@ -584,6 +597,53 @@ __global__ void __launch_bounds__(256) k_embed(const JobDev *jobs, JobDev one) {
     for (uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * 256)
         J.eb[which][w] = embed_word(e, J.L, w);
 }
+
+// ------------------------------------------------------------------ persistent batch of small jobs
+
+// Work items are taken from *counter until all are done. Item k of class c covers
+// jobs first_job + (k - first_item) * JPW .. + JPW - 1, JPW = 2^(14 - LG): a
+// 1024-thread workgroup runs JPW jobs of length 2^LG side by side, one per
+// 2^(LG-4)-thread group, with 2^14 words of LDS in total. Every workgroup exits
+// once the counter passes the last item.
+__device__ inline void small_item(int lg, const JobDev *jobs, uint64_t first, uint64_t count, uint32_t *lds,
+                                  uint32_t *red, const Tables &tb) {
+    switch (lg) {
+#define CASE(LG)                                                                                        \
+    case LG: {                                                                                          \
+        constexpr int NT = SmallTile<LG>::NT;                                                           \
+        const uint64_t g = threadIdx.x / NT;                                                            \
+        const bool valid = g < count;                                                                   \
+        small_body<LG>(jobs[first + (valid ? g : 0)], valid, lds + g * SmallTile<LG>::LDS_WORDS, red + 2 * g, tb); \
+        break;                                                                                          \
+    }
+        CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14)
+#undef CASE
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_small_persist(const JobDev *jobs, SmallClasses cls, uint32_t *counter,
+                                                        Tables tb) {
+    __shared__ uint32_t lds[(1 << 14) + (1 << 10)];
+    __shared__ uint32_t red[2 * 256];
+    __shared__ uint32_t item_s;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = item_s;
+        __syncthreads();
+        if (item >= cls.total_items) break;
+        int c = 0;
+        while (c + 1 < cls.n && item >= cls.first_item[c + 1]) ++c;
+        const int lg = cls.lg[c];
+        const uint64_t jpw = uint64_t(1) << (14 - lg);
+        const uint64_t first = cls.first_job[c] + (uint64_t)(item - cls.first_item[c]) * jpw;
+        const uint64_t end = cls.first_job[c] + cls.njobs[c];
+        small_item(lg, jobs, first, end - first < jpw ? end - first : jpw, lds, red, tb);
+        __syncthreads();  // LDS reuse by the next item
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
 
 // ------------------------------------------------------------------ pack, degenerate check
 
@@ -821,6 +881,13 @@ hipError_t launch_small(int lg, uint32_t njobs, const JobDev *jobs, const JobDev
         case 14: return small_one<14>(njobs, jobs, one, t, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_small_batch(const SmallClasses &cls, const JobDev *jobs, uint32_t *counter, unsigned workgroups,
+                              const Tables &t, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL(k_small_persist, dim3(workgroups), dim3(1024), 0, s, jobs, cls, counter, t);
+    return hipGetLastError();
 }
 
 hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, const JobDev *one, hipStream_t s) {

@@ -1,0 +1,98 @@
+"""Batched extraction: every job of a mixed batch equals the oracle and the same
+job run alone, bit for bit; invalid jobs are reported and skipped; replays of a
+cached batch signature with new inputs stay correct."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import show_case, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2402_09481_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def make_batch(count, seed, lo=6.0, hi=17.0):
+    params = W.batch_params(count, seed=seed, next_na=oracle.next_na, log_lo=lo, log_hi=hi)
+    jobs = []
+    g = W.rng(seed + 1)
+    for i, (kind, n, m, px, sub) in enumerate(params):
+        if i % 7 == 3:  # some Dodis jobs as well
+            n = oracle.next_na(n)
+            kind, m = "dodis", max(1, n // 2)
+        j = W.make_job(kind, n, m, px, sub, seed_order="linear" if (kind == "toeplitz" and i % 2) else "paper")
+        if kind == "dodis":
+            j.x[0] = (int(j.x[0]) | 1) & ~2
+        jobs.append(j)
+    return jobs
+
+
+def run_batch(ctx, jobs, unbatched=False, graph=False):
+    import torch
+    dev = []
+    for j in jobs:
+        z = torch.full((W.nwords(j.m),), -1, dtype=torch.int64, device="cuda")
+        st = torch.full((1,), 777, dtype=torch.int32, device="cuda")
+        dev.append({"kind": j.kind, "n": j.n, "m": j.m, "x": to_dev(j.x), "y": to_dev(j.y), "z": z, "status": st,
+                    "seed_order": j.seed_order})
+    rc, errs = ctx.batch(dev, sync=True, unbatched=unbatched, graph=graph)
+    torch.cuda.synchronize()
+    return rc, errs, [to_host(d["z"]) for d in dev], [int(d["status"].item()) for d in dev]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_oracle_and_single(ctx, graph):
+    jobs = make_batch(160, seed=5)
+    show_case("batch 160 jobs", graph)
+    rc, errs, zs, sts = run_batch(ctx, jobs, graph=graph)
+    assert rc == 0 and all(e == 0 for e in errs)
+    rc2, errs2, zs2, sts2 = run_batch(ctx, jobs, unbatched=True)
+    assert rc2 == 0
+    for j, z, z2, st in zip(jobs, zs, zs2, sts):
+        assert st == 0
+        code, want = oracle.extract(j.kind, j.x, j.y, j.n, j.m, j.seed_order)
+        assert code == 0
+        assert np.array_equal(z, want), (j.kind, j.n, j.m)
+        assert np.array_equal(z, z2)
+
+
+def test_batch_replay_with_new_inputs(ctx):
+    # same shapes (same batch signature, so the cached graph is replayed), new bits
+    a = make_batch(40, seed=9, lo=8, hi=16)
+    show_case("batch replay")
+    run_batch(ctx, a, graph=True)
+    b = []
+    for j in a:
+        g = W.rng(j.n * 31 + j.m)
+        x = W.bernoulli_bits(g, j.n, 0.4)
+        if j.kind == "dodis":
+            x[0] = (int(x[0]) | 1) & ~2
+        b.append(W.Job(j.kind, j.n, j.m, x, W.bernoulli_bits(g, j.seed_bits, 0.5), j.seed_order))
+    for _ in range(2):
+        rc, errs, zs, sts = run_batch(ctx, b, graph=True)
+        assert rc == 0
+        for j, z in zip(b, zs):
+            assert np.array_equal(z, oracle.extract(j.kind, j.x, j.y, j.n, j.m, j.seed_order)[1])
+
+
+def test_batch_reports_invalid_jobs(ctx):
+    jobs = make_batch(12, seed=13, lo=8, hi=12)
+    bad = W.Job("circulant", 11, 5, W.bernoulli_bits(W.rng(1), 11, 0.5), W.bernoulli_bits(W.rng(2), 12, 0.5))
+    degen = W.Job("dodis", 1019, 100, np.zeros(W.nwords(1019), np.uint64), W.bernoulli_bits(W.rng(3), 1019, 0.5))
+    jobs = jobs[:5] + [bad, degen] + jobs[5:]
+    show_case("batch invalid")
+    rc, errs, zs, sts = run_batch(ctx, jobs)
+    assert errs[5] == oracle.ENOTNA and rc == oracle.ENOTNA
+    assert errs[6] == 0 and sts[6] == oracle.EDEGENERATE and not zs[6].any()
+    for i, j in enumerate(jobs):
+        if i in (5, 6):
+            continue
+        assert errs[i] == 0 and sts[i] == 0
+        assert np.array_equal(zs[i], oracle.extract(j.kind, j.x, j.y, j.n, j.m, j.seed_order)[1])
