@@ -72,10 +72,10 @@ typedef struct ext_ctx ext_ctx;
 
 /* Create a context on HIP device `hip_device`: uploads the twiddle tables of
  * both fields and sets up the workspace pool, capped at hbm_budget_bytes
- * (0 = 90% of the device's free memory). tune_json: path of an autotune
- * table written by the library's tuner, or NULL for built-in defaults.
- * Returns EXT_OK and *out, or an error code and *out = NULL. */
-int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const char *tune_json);
+ * (0 = 90% of the device's free memory). tune_path: a tuning table written by
+ * ext_tune_save (or NULL for the built-in plans); a missing or malformed file
+ * is ignored. Returns EXT_OK and *out, or an error code and *out = NULL. */
+int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const char *tune_path);
 
 /* Synchronise the device, free all device memory of the context. NULL is a no-op. */
 void ext_destroy(ext_ctx *ctx);
@@ -157,6 +157,19 @@ int ext_mem_stats(ext_ctx *ctx, size_t *budget, size_t *in_use, size_t *reserved
 
 /* Release cached (not leased) workspace back to the device. */
 int ext_trim(ext_ctx *ctx);
+
+/* ---- tuning -------------------------------------------------------------
+ * A plan for transform length 2^lg in the field with word_bits (32 or 64):
+ * nlev = 0 runs each job in one workgroup (32-bit field, lg <= 14); nlev >= 2
+ * gives the log2 sizes of the passes, lgr[0..nlev-2] the strided ones and
+ * lgr[nlev-1] the contiguous one (sum = lg, each within the compiled tile
+ * sizes). ext_tune_set overrides the built-in plan for later calls (nlev < 0
+ * removes the override); EXT_EINVAL for an unsupported plan. ext_tune_get
+ * reports the plan in use. ext_tune_save writes every override as a text line
+ * "<word_bits> <lg> <nlev> <lgr...>". */
+int ext_tune_set(ext_ctx *ctx, int word_bits, int lg, int nlev, const int *lgr);
+int ext_tune_get(ext_ctx *ctx, int word_bits, int lg, int *nlev, int *lgr /* 4 entries */);
+int ext_tune_save(ext_ctx *ctx, const char *path);
 
 /* Primes with 2 as a primitive root (footnote of the Circulant definition;
  * utilities next_na_set / closest_na_set):

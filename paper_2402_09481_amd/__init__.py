@@ -64,11 +64,18 @@ def _stream_handle(stream):
 class Context:
     """An extractor context on one device (twiddle tables, workspace pool)."""
 
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, tune_json: str | None = None):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, tune=True):
+        """tune: True loads the packaged tuning table (tune_gfx950.txt) when present,
+        False keeps the built-in plans, a str is the path of a table."""
         lib = _lib.load()
         h = ctypes.c_void_p()
-        rc = lib.ext_create(ctypes.byref(h), int(device), int(hbm_budget_bytes),
-                            tune_json.encode() if tune_json else None)
+        if tune is True:
+            import os
+            path = os.path.join(_lib.HERE, "tune_gfx950.txt")
+            tune = path if os.path.exists(path) else None
+        elif tune is False:
+            tune = None
+        rc = lib.ext_create(ctypes.byref(h), int(device), int(hbm_budget_bytes), tune.encode() if tune else None)
         if rc != EXT_OK:
             raise ExtError(rc, "ext_create")
         self.handle = h
@@ -131,6 +138,30 @@ class Context:
         if check and rc != EXT_OK:
             raise ExtError(rc, "extract_" + kind)
         return z if check else (rc, z)
+
+    def tune_set(self, word_bits: int, lg: int, levels):
+        """Override the plan for transform length 2^lg: levels = [] for one workgroup per
+        job, a list of pass sizes (log2) otherwise, None to drop the override."""
+        if levels is None:
+            rc = self._lib.ext_tune_set(self.handle, word_bits, lg, -1, None)
+        else:
+            arr = (ctypes.c_int * 4)(*(list(levels) + [0] * (4 - len(levels))))
+            rc = self._lib.ext_tune_set(self.handle, word_bits, lg, len(levels), arr)
+        if rc != EXT_OK:
+            raise ExtError(rc, "ext_tune_set")
+
+    def tune_get(self, word_bits: int, lg: int):
+        nlev = ctypes.c_int()
+        arr = (ctypes.c_int * 4)()
+        rc = self._lib.ext_tune_get(self.handle, word_bits, lg, ctypes.byref(nlev), arr)
+        if rc != EXT_OK:
+            raise ExtError(rc, "ext_tune_get")
+        return list(arr[: nlev.value])
+
+    def tune_save(self, path: str):
+        rc = self._lib.ext_tune_save(self.handle, path.encode())
+        if rc != EXT_OK:
+            raise ExtError(rc, "ext_tune_save")
 
     def workspace_bytes(self, kind: str, n: int, m: int) -> int:
         return int(self._lib.ext_workspace_bytes(KINDS[kind], int(n), int(m)))

@@ -36,6 +36,7 @@ SYMBOLS = [
     "extract_batch", "extract_batch_unbatched", "ext_workspace_bytes", "ext_plan_length",
     "ext_mem_stats", "ext_trim", "ext_is_na_prime", "ext_next_na", "ext_closest_na",
     "ext_strerror", "ext_version", "ext_profile", "ext_profile_read",
+    "ext_tune_set", "ext_tune_get", "ext_tune_save",
 ]
 
 
@@ -105,6 +106,12 @@ def load() -> ctypes.CDLL:
     lib.ext_profile.restype = ctypes.c_int
     lib.ext_profile_read.argtypes = [vp, ctypes.c_char_p, sz]
     lib.ext_profile_read.restype = ctypes.c_int
+    lib.ext_tune_set.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.ext_tune_set.restype = ctypes.c_int
+    lib.ext_tune_get.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.ext_tune_get.restype = ctypes.c_int
+    lib.ext_tune_save.argtypes = [vp, ctypes.c_char_p]
+    lib.ext_tune_save.restype = ctypes.c_int
     lib.ext_version.argtypes = []
     lib.ext_version.restype = ctypes.c_char_p
     _lib = lib

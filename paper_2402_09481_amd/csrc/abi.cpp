@@ -378,6 +378,7 @@ struct ext_ctx {
     Tables tb[2];
     void *tb_mem[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     int force_field = 0;
+    std::map<int, Plan> tuned;  // key: field * 64 + lg
     hipStream_t capture_stream = nullptr;
     // pinned status words for EXT_SYNC calls without a status pointer
     std::vector<int32_t *> pinned_status;
@@ -399,6 +400,32 @@ struct ext_ctx {
     };
     std::vector<Mark> marks;
 };
+
+namespace {
+
+bool valid_plan(const Plan &p) {
+    if (p.small) return p.field == FIELD_BB && p.lg >= MIN_LG && p.lg <= max_small_lg() && p.nlev == 0;
+    if (p.nlev < 2 || p.nlev > 4) return false;
+    int sum = 0;
+    for (int i = 0; i < p.nlev; ++i) {
+        const int cap = i + 1 < p.nlev ? max_strided_lg(p.field) : max_contig_lg(p.field);
+        if (p.lgr[i] < MIN_LEVEL_LG || p.lgr[i] > cap) return false;
+        sum += p.lgr[i];
+    }
+    return sum == p.lg;
+}
+
+// The built-in plan, or the context's tuned one for the same field and length.
+int plan_for(ext_ctx *c, uint64_t Lmin, Plan &p) {
+    int rc = make_plan(Lmin, c ? c->force_field : 0, p);
+    if (rc != EXT_OK || !c || c->force_field) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    auto it = c->tuned.find(p.field * 64 + p.lg);
+    if (it != c->tuned.end()) p = it->second;
+    return EXT_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -629,7 +656,7 @@ int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint6
     if (rc) return rc;
     if ((rc = validate(sh, x, y, z, flags)) != EXT_OK) return rc;
     Plan p;
-    if ((rc = make_plan(sh.Lmin, c->force_field, p)) != EXT_OK) return rc;
+    if ((rc = plan_for(c, sh.Lmin, p)) != EXT_OK) return rc;
     if (hipSetDevice(c->device) != hipSuccess) return EXT_EDEVICE;
     const Layout lay = workspace_layout(p);
     Lease lease;
@@ -728,8 +755,7 @@ uint64_t ext_plan_length(int32_t kind, uint64_t n, uint64_t m, int32_t *word_bit
     return uint64_t(1) << p.lg;
 }
 
-int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const char *tune_json) {
-    (void)tune_json;
+int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const char *tune_path) {
     if (!out) return EXT_EINVAL;
     *out = nullptr;
     int ndev = 0;
@@ -778,6 +804,19 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
         return EXT_EDEVICE;
     }
     for (int f = 0; f < 2; ++f) c->tb[f] = Tables{c->tb_mem[f][0], c->tb_mem[f][1], c->tb_mem[f][2]};
+    if (tune_path) {
+        // lines "<word_bits> <lg> <nlev> <lgr...>"; anything unparsable or unsupported is skipped
+        if (FILE *f = fopen(tune_path, "r")) {
+            char line[256];
+            while (fgets(line, sizeof line, f)) {
+                if (line[0] == '#') continue;
+                int wb, lg, nlev, r[4] = {0, 0, 0, 0};
+                int k = sscanf(line, "%d %d %d %d %d %d %d", &wb, &lg, &nlev, &r[0], &r[1], &r[2], &r[3]);
+                if (k >= 3 && k == 3 + std::max(nlev, 0)) ext_tune_set(c, wb, lg, nlev, r);
+            }
+            fclose(f);
+        }
+    }
     *out = c;
     return EXT_OK;
 }
@@ -807,6 +846,63 @@ void ext_destroy(ext_ctx *c) {
     }
     if (c->capture_stream) hipStreamDestroy(c->capture_stream);
     delete c;
+}
+
+int ext_tune_set(ext_ctx *c, int word_bits, int lg, int nlev, const int *lgr) {
+    if (!c || (word_bits != 32 && word_bits != 64) || lg < MIN_LG || lg > 32) return EXT_EINVAL;
+    const int field = word_bits == 32 ? FIELD_BB : FIELD_GL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (nlev < 0) {
+        c->tuned.erase(field * 64 + lg);
+        return EXT_OK;
+    }
+    Plan p;
+    p.field = field;
+    p.lg = lg;
+    p.small = nlev == 0;
+    p.nlev = nlev;
+    for (int i = 0; i < nlev && i < 4; ++i) {
+        if (!lgr) return EXT_EINVAL;
+        p.lgr[i] = lgr[i];
+    }
+    if (!valid_plan(p)) return EXT_EINVAL;
+    c->tuned[field * 64 + lg] = p;
+    return EXT_OK;
+}
+
+int ext_tune_get(ext_ctx *c, int word_bits, int lg, int *nlev, int *lgr) {
+    if (!c || (word_bits != 32 && word_bits != 64) || lg < MIN_LG || lg > 32) return EXT_EINVAL;
+    const int field = word_bits == 32 ? FIELD_BB : FIELD_GL;
+    Plan p;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        auto it = c->tuned.find(field * 64 + lg);
+        if (it != c->tuned.end()) p = it->second;
+    }
+    if (p.lg == 0) {
+        const int rc = make_plan(uint64_t(1) << lg, field == FIELD_GL ? 2 : 1, p);
+        if (rc != EXT_OK) return rc;
+    }
+    if (nlev) *nlev = p.small ? 0 : p.nlev;
+    if (lgr)
+        for (int i = 0; i < 4; ++i) lgr[i] = p.lgr[i];
+    return EXT_OK;
+}
+
+int ext_tune_save(ext_ctx *c, const char *path) {
+    if (!c || !path) return EXT_EINVAL;
+    FILE *f = fopen(path, "w");
+    if (!f) return EXT_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    fprintf(f, "# word_bits lg nlev lgr...  (nlev 0: one workgroup per job)\n");
+    for (auto &kv : c->tuned) {
+        const Plan &p = kv.second;
+        fprintf(f, "%d %d %d", p.field == FIELD_BB ? 32 : 64, p.lg, p.small ? 0 : p.nlev);
+        for (int i = 0; i < (p.small ? 0 : p.nlev); ++i) fprintf(f, " %d", p.lgr[i]);
+        fprintf(f, "\n");
+    }
+    fclose(f);
+    return EXT_OK;
 }
 
 int ext_mem_stats(ext_ctx *c, size_t *budget, size_t *in_use, size_t *reserved) {
@@ -1122,7 +1218,7 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
         if (rc == EXT_OK && (j.flags & ~(EXT_SEED_LINEAR | EXT_SYNC))) rc = EXT_EINVAL;
         if (rc == EXT_OK && j.kind != EXT_KIND_TOEPLITZ && (j.flags & EXT_SEED_LINEAR)) rc = EXT_EINVAL;
         if (rc == EXT_OK) rc = validate(mb.shape, j.x, j.y, j.z, j.flags & EXT_SEED_LINEAR);
-        if (rc == EXT_OK) rc = make_plan(mb.shape.Lmin, c->force_field, mb.plan);
+        if (rc == EXT_OK) rc = plan_for(c, mb.shape.Lmin, mb.plan);
         j.err = rc;
         if (rc != EXT_OK) {
             if (first == EXT_OK) first = rc;
