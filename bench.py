@@ -68,6 +68,34 @@ def kernel_bytes(label: str, L: int, w: int, n: int, N: int, m: int) -> int:
     return 0
 
 
+PROFILE_BYTES = os.path.join(ROOT, "profiles", "toeplitz_n2p30_hbm_bytes.md")
+KERNEL_SOURCES = ["paper_2402_09481_amd/csrc/ntt.hip", "paper_2402_09481_amd/csrc/field.h",
+                  "paper_2402_09481_amd/csrc/kernels.h"]
+
+
+def profiled_traffic(label: str):
+    """HBM bytes (read + write, calibrated) of one launch of the kernel behind a trace
+    label, from the committed rocprofv3 summary — None if that summary does not exist or
+    was taken on different kernel sources."""
+    import hashlib
+    try:
+        text = open(PROFILE_BYTES).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for fn in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, fn), "rb").read())
+    if h.hexdigest() != blob.get("kernel_sources_sha256"):
+        return None
+    kind = label.split("[")[0]
+    f = dict(kv.split("=") for kv in label.split("[")[1].rstrip("]").split(",")[1:])
+    field = "FGL" if "u64" in label else "FBB"
+    name = "k_%s<%s, %s, %s>" % (kind, field, f["lgr"], f["mode"])
+    e = blob.get("per_launch", {}).get(name)
+    return None if e is None else e["read_bytes"] + e["write_bytes"]
+
+
 def cpu_baseline(job, seconds: float):
     """Oracle rows of the same workload for about `seconds` of one core."""
     import oracle
@@ -155,7 +183,8 @@ def run_headline(args):
                                "length 2^31 mod 2^64-2^32+1, 3-level multi-pass NTT",
                    "n": job.n, "m": job.m, "transform_length": L, "word_bytes": w},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                     "traffic": profiled_traffic(dom["kernel"]), "algo_bytes_per_launch": dom["algo_bytes"]},
         "path": {"algo_bytes": path_bytes, "achieved_GBs": round(path_bytes / (ms * 1e-3) / 1e9, 1),
                  "frac_of_hbm_roofline": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                  "roofline_Mbit_s": round(job.m / (path_bytes / (HBM_PEAK_GBS * 1e9)) / 1e6, 1)},

@@ -1,0 +1,83 @@
+"""The C-ABI library on the CPU: exported symbols match the header, host-only
+entry points (prime utilities, plan and workspace sizes, error strings) and the
+context-creation error path. No GPU compute is called."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2402_09481_amd import _lib
+    return _lib.load()
+
+
+def declared():
+    h = open(os.path.join(ROOT, "include", "extractor.h")).read()
+    h = re.sub(r"/\*.*?\*/", "", h, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ext_[a-z_]+|extract_[a-z_]+)\s*\(", h,
+                                 flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2402_09481_amd import _lib
+    names = declared()
+    assert len(names) >= 20
+    assert sorted(_lib.SYMBOLS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_na_utilities_match_oracle(lib):
+    for v in range(0, 4000):
+        assert bool(lib.ext_is_na_prime(v)) == oracle.is_na_prime(v), v
+    for v in [1 << 20, 10**6, 10**7 + 19, 1 << 30, 6_500_000_001, 1_738_000_001]:
+        assert lib.ext_next_na(v) == oracle.next_na(v)
+        assert lib.ext_closest_na(v) == oracle.closest_na(v)
+    assert lib.ext_closest_na(6_500_000_001) == 6_500_000_069
+
+
+def test_plan_lengths_and_workspace(lib):
+    wb = ctypes.c_int32()
+    cases = [(0, 4096, 2048, 8192, 32), (2, 1048589, 1 << 19, 1 << 22, 32), (0, 1 << 30, 1 << 29, 1 << 31, 64),
+             (1, 1048588, 1000, 1 << 22, 32), (0, 1, 1, 64, 32), (0, (1 << 26), (1 << 25), 1 << 27, 32)]
+    for kind, n, m, L, bits in cases:
+        assert lib.ext_plan_length(kind, n, m, ctypes.byref(wb)) == L
+        assert wb.value == bits
+    assert lib.ext_workspace_bytes(0, 4096, 2048) == 0  # one workgroup, no workspace
+    big = lib.ext_workspace_bytes(0, 1 << 30, 1 << 29)
+    assert 2 * (1 << 31) * 8 <= big < 2 * (1 << 31) * 8 + (1 << 30)
+    # invalid shapes
+    for kind, n, m in [(0, 10, 0), (0, 10, 11), (1, 10, 11), (2, 5, 6), (7, 10, 5), (0, (1 << 33), 1 << 31)]:
+        assert lib.ext_plan_length(kind, n, m, None) == 0
+        assert lib.ext_workspace_bytes(kind, n, m) == 0
+
+
+def test_error_strings(lib):
+    for code in range(0, -7, -1):
+        s = lib.ext_strerror(code).decode()
+        assert s and "unknown" not in s
+    assert "unknown" in lib.ext_strerror(-99).decode()
+    assert lib.ext_version().decode().startswith("paper_2402_09481_amd")
+
+
+def test_create_rejects_bad_device(lib):
+    h = ctypes.c_void_p()
+    rc = lib.ext_create(ctypes.byref(h), 1 << 20, 0, None)
+    assert rc == -6 and not h.value  # EXT_EDEVICE, no context
+    assert lib.ext_create(None, 0, 0, None) == -1
+    lib.ext_destroy(None)  # no-op
+
+
+def test_null_context_calls(lib):
+    assert lib.extract_toeplitz(None, None, 10, None, 5, None, 0, None, None) == -1
+    assert lib.extract_batch(None, None, 0, 0, None) == -1
+    assert lib.ext_mem_stats(None, None, None, None) == -1
+    assert lib.ext_profile(None, 1) == -1
+    assert lib.ext_tune_set(None, 32, 20, 2, None) == -1
