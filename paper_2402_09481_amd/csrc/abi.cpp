@@ -262,17 +262,20 @@ int shape_of(int kind, uint64_t n, uint64_t m, Shape &s) {
         s.Lmin = n + m - 1;
         s.out_len = m;
     } else if (kind == EXT_KIND_CIRCULANT) {
+        // computed as the linear-order Toeplitz extractor of rev([x, 0]) with the
+        // seed y || y_{0..m-2} (length (n+1) + m - 1)
         if (n < 1 || m < 1 || m > n) return EXT_EINVAL;
         if (n > (uint64_t(1) << 40)) return EXT_ETOOLARGE;
-        s.nfold = n + 1;
-        s.Lmin = 2 * (n + 1) - 1;
-        s.out_len = m + n + 1;
+        s.nfold = 0;
+        s.Lmin = (n + 1) + m - 1;
+        s.out_len = m;
     } else if (kind == EXT_KIND_DODIS) {
+        // computed as the linear-order Toeplitz extractor of rev(x) with y || y_{0..m-2}
         if (n < 1 || m < 1 || m > n) return EXT_EINVAL;
         if (n > (uint64_t(1) << 40)) return EXT_ETOOLARGE;
-        s.nfold = n;
-        s.Lmin = 2 * n - 1;
-        s.out_len = m + n;
+        s.nfold = 0;
+        s.Lmin = n + m - 1;
+        s.out_len = m;
     } else {
         return EXT_EINVAL;
     }
@@ -339,19 +342,18 @@ JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint6
     j.K = pointwise_K(p);
     if (s.kind == EXT_KIND_TOEPLITZ) {
         const uint64_t N = s.n + s.m - 1;
-        j.ex = Emb{x, s.n, 0, 0, 0, EMB_PREFIX, 0};
+        j.ex = Emb{x, s.n, 0, 0, 0, 0, EMB_PREFIX, 0};
         const uint64_t rot = (flags & EXT_SEED_LINEAR) ? 0 : (s.m % N);
-        j.ey = Emb{y, N, s.n - 1, N, rot, EMB_SEED, 0};
-        j.degen_n = 0;
-    } else if (s.kind == EXT_KIND_CIRCULANT) {
-        const uint64_t n = s.n + 1;
-        j.ex = Emb{x, s.n, 0, n, 0, EMB_REVERSE, 0};
-        j.ey = Emb{y, n, 0, 0, 0, EMB_PREFIX, 0};
+        j.ey = Emb{y, N, s.n - 1, N, rot, N, EMB_SEED, 0};
         j.degen_n = 0;
     } else {
-        j.ex = Emb{x, s.n, 0, s.n, 0, EMB_REVERSE, 0};
-        j.ey = Emb{y, s.n, 0, 0, 0, EMB_PREFIX, 0};
-        j.degen_n = s.n;
+        // circulant length n (Circulant: n_in + 1 with x' = [x, 0]); x reversed, the
+        // seed repeated with period n, output z_i = XOR_j s_{i-j+n-1} rev(x')_j
+        const uint64_t n = s.kind == EXT_KIND_CIRCULANT ? s.n + 1 : s.n;
+        const uint64_t N = n + s.m - 1;
+        j.ex = Emb{x, s.n, 0, n, 0, 0, EMB_REV, 0};
+        j.ey = Emb{y, n, n - 1, N, 0, n, EMB_SEED, 0};
+        j.degen_n = s.kind == EXT_KIND_DODIS ? s.n : 0;
     }
     return j;
 }

@@ -8,16 +8,22 @@
 namespace ext {
 
 // Embedding of a packed bit string into coefficient vector position i of a
-// length-L cyclic convolution (Alg. 1 and Alg. 2 embeddings, written as index maps):
-//   PREFIX  (Toeplitz input x, Dodis/Circulant seed y): i < len ? b_i : 0
-//   SEED    (Toeplitz seed): k = (i + a) mod L; k < N ? b_{(k + rot) mod N} : 0.
-//           With a = n - 1 this places s_k at (k - n + 1) mod L (linear order,
-//           rot = 0); rot = m gives the paper's order of eq. toep, for which the
-//           placement is Alg. 2's: v'[i] = y_i (i < m), v'[L-n+1+t] = y_{m+t}.
-//   REVERSE (Dodis/Circulant input): i < N ? b'_{(N - i) mod N} : 0, where
-//           b'_j = (j < len ? b_j : 0) — the reversal R(x) of the Dodis
-//           convolution form, on x' = [x, 0] for Circulant (len = N - 1).
-enum EmbMode : uint32_t { EMB_PREFIX = 0, EMB_SEED = 1, EMB_REVERSE = 2 };
+// length-L cyclic convolution, written as index maps:
+//   PREFIX  (Toeplitz input x): i < len ? b_i : 0
+//   SEED    (seed): k = (i + a) mod L; k < N ? b_{(k + rot) mod P} : 0. With
+//           a = n - 1 the seed string s_k lands at (k - n + 1) mod L, so output i
+//           of the cyclic convolution is z_i = XOR_j s_{i-j+n-1} x_j (linear
+//           order, Toeplitz: P = N, rot = 0); rot = m gives the paper's order of
+//           eq. toep (Alg. 2's placement v'[i] = y_i for i < m, v'[L-n+1+t] =
+//           y_{m+t}). Dodis/Circulant use P = n, rot = 0: s_k = y_{k mod n}.
+//   REV     (Dodis/Circulant input): i < N ? b'_{N-1-i} : 0 with
+//           b'_j = (j < len ? b_j : 0): the input reversed (Circulant: x' = [x, 0],
+//           len = N - 1).
+// Dodis(x, y)_i = XOR_j x_{(j-i) mod n} y_j equals the linear-order Toeplitz
+// extractor of rev(x) with the seed y || y_{0..m-2}: both sides are
+// XOR_{j'} x_{j'} y_{(i+j') mod n}. That needs a transform of length n + m - 1
+// instead of the 2n - 1 (plus a wrap-around fold) of the R(x) * y form of Alg. 1.
+enum EmbMode : uint32_t { EMB_PREFIX = 0, EMB_SEED = 1, EMB_REV = 2 };
 
 struct Emb {
     const uint64_t *bits;
@@ -25,6 +31,7 @@ struct Emb {
     uint64_t a;
     uint64_t N;
     uint64_t rot;
+    uint64_t P;  // period of the seed string (SEED)
     uint32_t mode;
     uint32_t pad_;
 };
@@ -41,7 +48,7 @@ struct JobDev {
     Emb ex, ey;        // embeddings of the input (into A) and the seed (into B)
     uint64_t L;        // transform length
     uint64_t m;        // output bits
-    uint64_t nfold;    // 0 (Toeplitz) or n (Dodis/Circulant: z_i = c_i ^ c_{i+n})
+    uint64_t nfold;    // 0, or n for a wrap-around fold z_i = c_i ^ c_{i+n} (unused by the built-in shapes)
     uint64_t out_len;  // coefficients whose parity is needed: m or m + n
     uint64_t degen_n;  // bits of x checked for all-0/all-1 (Dodis), 0 = no check
     uint64_t K;        // pointwise constant: folds L^-1 (and Montgomery factors)

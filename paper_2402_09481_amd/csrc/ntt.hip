@@ -58,18 +58,21 @@ __host__ __device__ inline uint32_t getbit(const uint64_t *b, uint64_t i) {
     return (uint32_t)(b[i >> 6] >> (i & 63)) & 1u;
 }
 
+__host__ __device__ inline uint64_t mod_small(uint64_t v, uint64_t P) {
+    while (v >= P) v -= P;  // v < 3P at every call site
+    return v;
+}
+
 __host__ __device__ inline uint32_t emb_bit(const Emb &e, uint64_t i, uint64_t L) {
     if (e.mode == EMB_PREFIX) return i < e.len ? getbit(e.bits, i) : 0u;
     if (e.mode == EMB_SEED) {
         uint64_t k = i + e.a;
         if (k >= L) k -= L;
         if (k >= e.N) return 0u;
-        uint64_t s = k + e.rot;
-        if (s >= e.N) s -= e.N;
-        return getbit(e.bits, s);
+        return getbit(e.bits, mod_small(k + e.rot, e.P));
     }
     if (i >= e.N) return 0u;
-    uint64_t j = i ? e.N - i : 0;
+    const uint64_t j = e.N - 1 - i;
     return j < e.len ? getbit(e.bits, j) : 0u;
 }
 
@@ -556,33 +559,24 @@ __host__ __device__ inline uint64_t embed_word(const Emb &e, uint64_t L, uint64_
                 pos += (int)umin64(64 - pos, L - k);
                 continue;
             }
-            uint64_t src = k + e.rot;
-            if (src >= e.N) src -= e.N;
-            const int run = (int)umin64(64 - pos, umin64(e.N - k, e.N - src));
+            const uint64_t src = mod_small(k + e.rot, e.P);
+            const int run = (int)umin64(64 - pos, umin64(e.N - k, e.P - src));
             out |= bits_at(e.bits, src, run) << pos;
             pos += run;
         }
         return out;
     }
-    // REVERSE: position i < N holds b'_{(N - i) mod N}, b'_j = j < len ? b_j : 0
+    // REV: position i < N holds b'_{N-1-i}, b'_j = j < len ? b_j : 0
     for (int t = 0; t < 64;) {
         const uint64_t i = i0 + t;
         if (i >= e.N) break;
-        if (i == 0) {
-            out |= (uint64_t)(e.len ? getbit(e.bits, 0) : 0u);
-            ++t;
+        const uint64_t j = e.N - 1 - i;  // positions i.. read j, j-1, ..
+        if (j >= e.len) {                // sources beyond len are zero: skip to j = len - 1
+            t += (int)umin64(j - e.len + 1, (uint64_t)(64 - t));
             continue;
         }
-        // positions i .. i+run-1 read j = N-i down to N-i-run+1 (all >= 1)
-        const uint64_t j = e.N - i;
-        int run = (int)umin64(64 - t, umin64(j, e.N - i));
-        if (j >= e.len) {  // sources beyond len are zero; skip to j = len - 1
-            const uint64_t skip = j - e.len + 1;
-            t += (int)umin64(skip, (uint64_t)(64 - t));
-            continue;
-        }
-        const uint64_t jlo = j - run + 1;
-        const uint64_t rev = __builtin_bitreverse64(bits_at(e.bits, jlo, run)) >> (64 - run);
+        const int run = (int)umin64(64 - t, j + 1);
+        const uint64_t rev = __builtin_bitreverse64(bits_at(e.bits, j - run + 1, run)) >> (64 - run);
         out |= rev << t;
         t += run;
     }

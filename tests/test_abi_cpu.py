@@ -45,8 +45,9 @@ def test_na_utilities_match_oracle(lib):
 
 def test_plan_lengths_and_workspace(lib):
     wb = ctypes.c_int32()
-    cases = [(0, 4096, 2048, 8192, 32), (2, 1048589, 1 << 19, 1 << 22, 32), (0, 1 << 30, 1 << 29, 1 << 31, 64),
-             (1, 1048588, 1000, 1 << 22, 32), (0, 1, 1, 64, 32), (0, (1 << 26), (1 << 25), 1 << 27, 32)]
+    cases = [(0, 4096, 2048, 8192, 32), (2, 1048589, 1 << 19, 1 << 21, 32), (0, 1 << 30, 1 << 29, 1 << 31, 64),
+             (1, 1048588, 1000, 1 << 21, 32), (2, 1048589, 1048589, 1 << 22, 32), (0, 1, 1, 64, 32),
+             (0, (1 << 26), (1 << 25), 1 << 27, 32)]
     for kind, n, m, L, bits in cases:
         assert lib.ext_plan_length(kind, n, m, ctypes.byref(wb)) == L
         assert wb.value == bits

@@ -364,3 +364,25 @@ def test_preconditions():
     assert oracle.check("dodis", 11, 3, z) == oracle.EDEGENERATE
     assert oracle.check("dodis", 11, 3, o) == oracle.EDEGENERATE
     assert oracle.dodis(z, z, 11, 3)[0] == oracle.EDEGENERATE
+
+
+def test_dodis_and_circulant_equal_toeplitz_reduction():
+    """Dodis(x, y) = linear-order Toeplitz(rev(x), y || y_{0..m-2}) and Circulant(x, y) =
+    the same with x' = [x, 0]: both sides are XOR_j x_j y_{(i+j) mod n}. The GPU path
+    computes these two extractors this way (transform length n + m - 1)."""
+    g = W.rng(123)
+    for n in (3, 5, 11, 13, 59, 61, 83, 787, 1019):
+        assert oracle.is_na_prime(n)
+        for m in sorted({1, n // 3 or 1, n - 1, n}):
+            x, y = rand_bits(g, n), rand_bits(g, n)
+            x[0], x[1] = 1, 0
+            s = np.concatenate([y, y[: m - 1]])
+            _, zd = oracle.dodis(W.pack_bits(x), W.pack_bits(y), n, m)
+            _, zt = oracle.toeplitz(W.pack_bits(x[::-1].copy()), W.pack_bits(s), n, m, "linear")
+            assert (zd == zt).all(), (n, m)
+            if m <= n - 1:
+                xc = x[: n - 1]
+                xp = np.concatenate([xc, [0]]).astype(np.uint8)
+                _, zc = oracle.circulant(W.pack_bits(xc), W.pack_bits(y), n - 1, m)
+                _, zt2 = oracle.toeplitz(W.pack_bits(xp[::-1].copy()), W.pack_bits(s), n, m, "linear")
+                assert (zc == zt2).all(), (n, m)
