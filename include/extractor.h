@@ -67,6 +67,14 @@ extern "C" {
  * afterwards. Worth it when the same signature repeats; without the flag the
  * grouped launches are enqueued directly. */
 #define EXT_GRAPH 4u
+/* Single calls: keep the seed's transform in HBM and reuse it. A strong seeded
+ * extractor may use one seed for many input blocks (the theorem on extractors
+ * with near-perfect seeds used t times); the cache is keyed by the seed pointer and the
+ * shape (kind, n, m, seed order), so the caller must not change the seed bits
+ * at that address while they are cached (ext_seed_cache_clear drops them).
+ * A hit skips one of the three transforms. Sizes that run in one workgroup
+ * ignore the flag. */
+#define EXT_SEED_CACHED 8u
 
 typedef struct ext_ctx ext_ctx;
 
@@ -157,6 +165,10 @@ int ext_mem_stats(ext_ctx *ctx, size_t *budget, size_t *in_use, size_t *reserved
 
 /* Release cached (not leased) workspace back to the device. */
 int ext_trim(ext_ctx *ctx);
+
+/* Forget every cached seed transform (waits for calls still using them) and
+ * report bytes / entries held before, if the pointers are not NULL. */
+int ext_seed_cache_clear(ext_ctx *ctx, size_t *bytes, size_t *entries);
 
 /* ---- tuning -------------------------------------------------------------
  * A plan for transform length 2^lg in the field with word_bits (32 or 64):

@@ -101,6 +101,12 @@ class Context:
     def trim(self):
         self._lib.ext_trim(self.handle)
 
+    def seed_cache_clear(self):
+        """Drop every cached seed transform; returns (bytes, entries) held before."""
+        b, e = ctypes.c_size_t(), ctypes.c_size_t()
+        self._lib.ext_seed_cache_clear(self.handle, ctypes.byref(b), ctypes.byref(e))
+        return b.value, e.value
+
     def profile(self, enable: bool = True):
         """Bracket every kernel launch of later extraction calls with HIP events."""
         self._lib.ext_profile(self.handle, 1 if enable else 0)
@@ -120,11 +126,14 @@ class Context:
 
     # -- raw calls (device tensors in, device tensor out) --------------------------------
     def extract(self, kind: str, x, y, n: int, m: int, z=None, seed_order: str = "paper", sync: bool = False,
-                status=None, stream=None, check: bool = True) -> "object":
+                status=None, stream=None, check: bool = True, cache_seed: bool = False) -> "object":
+        """cache_seed: keep / reuse the seed's transform (the seed bits at y must not
+        change while cached; see seed_cache_clear)."""
         import torch
         if z is None:
             z = torch.empty(words(m), dtype=torch.int64, device=x.device)
-        flags = (EXT_SEED_LINEAR if seed_order == "linear" else 0) | (EXT_SYNC if sync else 0)
+        flags = (EXT_SEED_LINEAR if seed_order == "linear" else 0) | (EXT_SYNC if sync else 0) | \
+            (_lib.EXT_SEED_CACHED if cache_seed else 0)
         st = ctypes.c_void_p(status.data_ptr()) if status is not None else None
         s = _stream_handle(stream)
         if kind == "toeplitz":

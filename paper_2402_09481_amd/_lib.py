@@ -23,6 +23,7 @@ EXT_SEED_PAPER = 0
 EXT_SEED_LINEAR = 1
 EXT_SYNC = 2
 EXT_GRAPH = 4
+EXT_SEED_CACHED = 8
 
 EXT_KIND_TOEPLITZ = 0
 EXT_KIND_CIRCULANT = 1
@@ -36,7 +37,7 @@ SYMBOLS = [
     "extract_batch", "extract_batch_unbatched", "ext_workspace_bytes", "ext_plan_length",
     "ext_mem_stats", "ext_trim", "ext_is_na_prime", "ext_next_na", "ext_closest_na",
     "ext_strerror", "ext_version", "ext_profile", "ext_profile_read",
-    "ext_tune_set", "ext_tune_get", "ext_tune_save",
+    "ext_tune_set", "ext_tune_get", "ext_tune_save", "ext_seed_cache_clear",
 ]
 
 
@@ -112,6 +113,8 @@ def load() -> ctypes.CDLL:
     lib.ext_tune_get.restype = ctypes.c_int
     lib.ext_tune_save.argtypes = [vp, ctypes.c_char_p]
     lib.ext_tune_save.restype = ctypes.c_int
+    lib.ext_seed_cache_clear.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+    lib.ext_seed_cache_clear.restype = ctypes.c_int
     lib.ext_version.argtypes = []
     lib.ext_version.restype = ctypes.c_char_p
     _lib = lib

@@ -304,7 +304,7 @@ uint64_t seed_bits(const Shape &s) {
 
 int validate(const Shape &s, const uint64_t *x, const uint64_t *y, const uint64_t *z, uint32_t flags) {
     if (!x || !y || !z) return EXT_EINVAL;
-    if (flags & ~(EXT_SEED_LINEAR | EXT_SYNC)) return EXT_EINVAL;
+    if (flags & ~(EXT_SEED_LINEAR | EXT_SYNC | EXT_SEED_CACHED)) return EXT_EINVAL;
     const size_t zb = words(s.m) * 8;
     if (overlaps(z, zb, x, words(s.n) * 8) || overlaps(z, zb, y, words(seed_bits(s)) * 8)) return EXT_EINVAL;
     return check_primes(s);
@@ -329,6 +329,7 @@ JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint6
         j.A = ws + l.a;
         j.B = ws + l.b;
         j.pb = (uint64_t *)(ws + l.pb);
+        j.S = j.A;
         j.eb[0] = (uint64_t *)(ws + l.eb0);
         j.eb[1] = (uint64_t *)(ws + l.eb1);
         j.flags = (uint32_t *)(ws + l.flags);
@@ -394,6 +395,18 @@ struct ext_ctx {
         bool ever = false;
     };
     std::map<std::string, GraphEntry> graphs;
+    // transformed-seed cache
+    struct SeedEntry {
+        char *ptr = nullptr;
+        size_t bytes = 0;
+        hipEvent_t ready = nullptr;  // the seed transform is complete
+        hipEvent_t used = nullptr;   // the last call that read it is complete
+        uint64_t tick = 0;
+        int busy = 0;                // calls between lookup and recording `used`
+    };
+    std::map<std::string, SeedEntry> seeds;
+    size_t seed_bytes = 0;
+    uint64_t seed_tick = 0;
     // tracing
     bool profile = false;
     struct Mark {
@@ -541,8 +554,13 @@ std::string pass_label(const char *what, int field, int lgr, int mode, int which
 
 // Enqueue the whole extraction for njobs jobs sharing one plan. jobs_dev: device
 // descriptors (batched launches) or nullptr with `one` for a single job.
+// COLD: both transforms, product, inverse, parity. SEED_ONLY: the seed's full
+// forward transform into B (a seed-cache entry). WARM: the input's transform
+// fused with the cached seed spectrum S, inverse in A, parity.
+enum Phase { PH_COLD = 0, PH_SEED_ONLY = 1, PH_WARM = 2 };
+
 hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs_dev, const JobDev *one,
-                   uint64_t max_m, bool any_degen, hipStream_t s, bool capturing = false) {
+                   uint64_t max_m, bool any_degen, hipStream_t s, bool capturing = false, Phase ph = PH_COLD) {
     const Tables &tb = c->tb[p.field];
     Tracer tr(c, s, capturing);
     if (p.small) {
@@ -557,7 +575,11 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
     e = launch_embed(njobs, L, jobs_dev, one, s);
     tr.end("embed");
     if (e != hipSuccess) return e;
+    // arrays: `fwd` lists the operands transformed here; the fused pass runs on `fused`
+    const int fused = ph == PH_WARM ? 0 : 1;
     for (int which = 0; which < 2; ++which) {
+        if (ph == PH_SEED_ONLY && which == 0) continue;
+        if (ph == PH_WARM && which == 1) continue;
         uint64_t Mprev = L;
         for (int i = 0; i + 1 < p.nlev; ++i) {
             const Geometry g = strided_geometry(p.field, p.lgr[i]);
@@ -583,7 +605,7 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         PassLaunch pl;
         pl.field = p.field;
         pl.lgr = lc;
-        pl.mode = which == 0 ? C_FWD : C_FUSED;
+        pl.mode = (ph == PH_SEED_ONLY || (ph == PH_COLD && which == 0)) ? C_FWD : C_FUSED;
         pl.which = which;
         pl.S = 0;
         pl.Mprev = 0;
@@ -597,6 +619,7 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         tr.end(pass_label("contig", p.field, pl.lgr, pl.mode, which));
         if (e != hipSuccess) return e;
     }
+    if (ph == PH_SEED_ONLY) return hipSuccess;
     // inverse: strided levels backwards; level 0 writes packed parity
     std::vector<uint64_t> mp(p.nlev);
     uint64_t M = L;
@@ -610,7 +633,7 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         pl.field = p.field;
         pl.lgr = p.lgr[i];
         pl.mode = i == 0 ? S_INV_PARITY : S_INV;
-        pl.which = 1;
+        pl.which = fused;
         pl.Mprev = mp[i];
         pl.S = mp[i] >> p.lgr[i];
         pl.tiles = (L / mp[i]) * (pl.S / g.C);
@@ -619,7 +642,7 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         pl.one = one;
         tr.begin();
         e = launch_strided(pl, tb, s);
-        tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, 1));
+        tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, fused));
         if (e != hipSuccess) return e;
     }
     tr.begin();
@@ -650,6 +673,72 @@ void give_pinned_status(ext_ctx *c, int32_t *p) {
     c->pinned_status.push_back(p);
 }
 
+void seed_free(ext_ctx::SeedEntry &se) {
+    hipEventSynchronize(se.used);
+    hipEventDestroy(se.ready);
+    hipEventDestroy(se.used);
+    hipFree(se.ptr);
+}
+
+// The cached spectrum of this call's seed, computing it (on stream s, into a new
+// entry) on a miss. Entries are evicted least recently used, once the calls that
+// read them are done, to keep the cache within a quarter of the budget. Returns
+// nullptr (and leaves e = hipSuccess) when no entry can be made: the caller then
+// runs the cold path.
+ext_ctx::SeedEntry *seed_entry(ext_ctx *c, const Shape &sh, const Plan &p, const uint64_t *y, uint32_t flags,
+                               hipStream_t s, const JobDev &jd, hipError_t &e) {
+    char key[160];
+    snprintf(key, sizeof key, "%p:%d:%llu:%llu:%u:%d:%d", (const void *)y, sh.kind, (unsigned long long)sh.n,
+             (unsigned long long)sh.m, flags & EXT_SEED_LINEAR, p.field, p.lg);
+    const size_t bytes = (size_t(1) << p.lg) * (p.field == FIELD_BB ? 4 : 8);
+    std::unique_lock<std::mutex> g(c->mu);
+    auto it = c->seeds.find(key);
+    if (it != c->seeds.end()) {
+        it->second.tick = ++c->seed_tick;
+        it->second.busy++;
+        ext_ctx::SeedEntry *se = &it->second;
+        g.unlock();
+        e = hipStreamWaitEvent(s, se->ready, 0);
+        return se;
+    }
+    const size_t cap = c->budget / 4;
+    while (c->seed_bytes + bytes > cap) {
+        auto victim = c->seeds.end();
+        for (auto jt = c->seeds.begin(); jt != c->seeds.end(); ++jt)
+            if (!jt->second.busy && (victim == c->seeds.end() || jt->second.tick < victim->second.tick)) victim = jt;
+        if (victim == c->seeds.end()) break;
+        c->seed_bytes -= victim->second.bytes;
+        c->reserved -= victim->second.bytes;
+        seed_free(victim->second);
+        c->seeds.erase(victim);
+    }
+    if (c->seed_bytes + bytes > cap || c->reserved + bytes > c->budget) return nullptr;
+    ext_ctx::SeedEntry se;
+    if (hipMalloc((void **)&se.ptr, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (hipEventCreateWithFlags(&se.ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&se.used, hipEventDisableTiming) != hipSuccess) {
+        hipFree(se.ptr);
+        e = hipErrorOutOfMemory;
+        return nullptr;
+    }
+    se.bytes = bytes;
+    se.tick = ++c->seed_tick;
+    se.busy = 1;
+    c->seed_bytes += bytes;
+    c->reserved += bytes;
+    ext_ctx::SeedEntry *ent = &(c->seeds[key] = se);
+    g.unlock();
+    JobDev sj = jd;
+    sj.B = ent->ptr;  // the seed's full transform lands in the entry
+    e = enqueue(c, p, 1, nullptr, &sj, sh.m, false, s, false, PH_SEED_ONLY);
+    if (e == hipSuccess) e = hipEventRecord(ent->ready, s);
+    if (e == hipSuccess) e = hipEventRecord(ent->used, s);
+    return ent;
+}
+
 int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint64_t *y, uint64_t m, uint64_t *z,
                 uint32_t flags, int32_t *status, hipStream_t s) {
     if (!c) return EXT_EINVAL;
@@ -675,7 +764,24 @@ int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint6
         st = mine;
     }
     JobDev jd = make_jobdev(sh, p, x, y, z, st, flags, lease.ptr);
-    hipError_t e = enqueue(c, p, 1, nullptr, &jd, sh.m, jd.degen_n != 0, s);
+    hipError_t e = hipSuccess;
+    ext_ctx::SeedEntry *se =
+        (flags & EXT_SEED_CACHED) && !p.small ? seed_entry(c, sh, p, y, flags, s, jd, e) : nullptr;
+    if (se && e != hipSuccess) {
+        std::lock_guard<std::mutex> g(c->mu);
+        se->busy--;
+    }
+    if (e == hipSuccess) {
+        if (se) {
+            jd.S = se->ptr;
+            e = enqueue(c, p, 1, nullptr, &jd, sh.m, jd.degen_n != 0, s, false, PH_WARM);
+            if (e == hipSuccess) e = hipEventRecord(se->used, s);
+            std::lock_guard<std::mutex> g(c->mu);
+            se->busy--;
+        } else {
+            e = enqueue(c, p, 1, nullptr, &jd, sh.m, jd.degen_n != 0, s);
+        }
+    }
     pool_release(c, lease, s);
     if (e != hipSuccess) {
         if (mine) give_pinned_status(c, mine);
@@ -842,6 +948,7 @@ void ext_destroy(ext_ctx *c) {
             if (c->tb_mem[f][k]) hipFree(c->tb_mem[f][k]);
     for (auto p : c->pinned_status) hipHostFree(p);
     pinned_release_all(c);
+    for (auto &kv : c->seeds) seed_free(kv.second);
     for (auto &mk : c->marks) {
         hipEventDestroy(mk.a);
         hipEventDestroy(mk.b);
@@ -904,6 +1011,18 @@ int ext_tune_save(ext_ctx *c, const char *path) {
         fprintf(f, "\n");
     }
     fclose(f);
+    return EXT_OK;
+}
+
+int ext_seed_cache_clear(ext_ctx *c, size_t *bytes, size_t *entries) {
+    if (!c) return EXT_EINVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (bytes) *bytes = c->seed_bytes;
+    if (entries) *entries = c->seeds.size();
+    for (auto &kv : c->seeds) seed_free(kv.second);
+    c->reserved -= c->seed_bytes;
+    c->seed_bytes = 0;
+    c->seeds.clear();
     return EXT_OK;
 }
 

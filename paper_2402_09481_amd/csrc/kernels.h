@@ -40,6 +40,7 @@ struct Emb {
 struct JobDev {
     void *A;           // L words: the input transform, then its spectrum
     void *B;           // L words: the seed transform, then the product, then the convolution
+    void *S;           // spectrum operand of the fused pass: A, or a cached seed spectrum
     uint64_t *pb;      // packed parity of coefficients [0, out_len) (+1 spare word)
     uint64_t *eb[2];   // the two embedded coefficient vectors as L-bit strings (multi-pass only)
     uint32_t *flags;   // degenerate check: flags[0] = any one bit, flags[1] = any zero bit

@@ -29,10 +29,10 @@
 //              S_FWD: column transform, then twiddle, in place
 //              S_INV: twiddle^-1, then inverse column transform, in place
 //              S_INV_PARITY: as S_INV, then canonical residue mod 2, packed
-//   contiguous C_FWD: row transform (last level of the input's transform)
-//              C_FUSED: seed row transform, times the input's spectrum times
-//              L^-1, inverse row transform (last forward level of the seed,
-//              the pointwise product, first inverse level)
+//   contiguous C_FWD: row transform (last level of a forward transform)
+//              C_FUSED: row transform of one operand, times the other operand's
+//              spectrum (S) times L^-1, inverse row transform (last forward
+//              level, the pointwise product, first inverse level)
 //   small      whole extraction of one job in one workgroup (L <= 2^14)
 #include <algorithm>
 #include <cstring>
@@ -354,8 +354,8 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
     __shared__ T lds[Tl::LDS_WORDS];
 
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
-    T *data = (T *)((MODE == C_FUSED || a.which) ? J.B : J.A);
-    const T *spec = (const T *)J.A;
+    T *data = (T *)(a.which ? J.B : J.A);
+    const T *spec = (const T *)J.S;
     const uint64_t base = (uint64_t)blockIdx.x * C * R;
 
     T v[EPT];

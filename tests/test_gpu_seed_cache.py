@@ -1,0 +1,75 @@
+"""Cached seed transforms: calls that reuse a seed's cached spectrum give the same
+bits as cold calls and as the oracle; clearing the cache and changing the seed
+gives the new seed's result."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_helpers import show_case, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def seed_len(kind, n, m):
+    return {"toeplitz": n + m - 1, "circulant": n + 1, "dodis": n}[kind]
+
+
+def check(ctx, kind, n, m, order="paper", blocks=3, seed=0):
+    g = W.rng(seed)
+    y = W.bernoulli_bits(g, seed_len(kind, n, m), 0.5)
+    yd = to_dev(y)
+    for b in range(blocks):
+        x = W.bernoulli_bits(g, n, 0.4)
+        if kind == "dodis":
+            x[0] = (int(x[0]) | 1) & ~2
+        show_case("seed cache", kind, n, m, order, b)
+        z = ctx.extract(kind, to_dev(x), yd, n, m, seed_order=order, sync=True, cache_seed=True)
+        want = oracle.extract(kind, x, y, n, m, order)[1]
+        assert np.array_equal(to_host(z), want), (kind, n, m, b)
+    return yd
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2402_09481_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("kind,n,m,order", [("toeplitz", 100003, 50001, "paper"), ("toeplitz", 100003, 50001, "linear"),
+                                            ("toeplitz", 1 << 19, 1 << 18, "paper"), ("dodis", 65587, 30000, "paper"),
+                                            ("circulant", 65586, 65586, "paper")])
+def test_cached_seed_matches_oracle(ctx, kind, n, m, order):
+    check(ctx, kind, n, m, order, seed=n + m)
+
+
+def test_cache_clear_and_new_seed_bits(ctx):
+    n, m = 70001, 30000
+    g = W.rng(3)
+    y1 = W.bernoulli_bits(g, n + m - 1, 0.5)
+    x = W.bernoulli_bits(g, n, 0.5)
+    yd = to_dev(y1)
+    z1 = ctx.extract("toeplitz", to_dev(x), yd, n, m, sync=True, cache_seed=True)
+    assert np.array_equal(to_host(z1), oracle.extract("toeplitz", x, y1, n, m)[1])
+    y2 = W.bernoulli_bits(g, n + m - 1, 0.5)
+    yd.copy_(to_dev(y2))  # same address, new bits: the cache must be cleared
+    b, e = ctx.seed_cache_clear()
+    assert e >= 1 and b > 0
+    z2 = ctx.extract("toeplitz", to_dev(x), yd, n, m, sync=True, cache_seed=True)
+    assert np.array_equal(to_host(z2), oracle.extract("toeplitz", x, y2, n, m)[1])
+
+
+def test_cached_seed_64bit_field():
+    import paper_2402_09481_amd as P
+    os.environ["EXT_FORCE_FIELD"] = "gl"
+    try:
+        c = P.Context(0)
+    finally:
+        del os.environ["EXT_FORCE_FIELD"]
+    check(c, "toeplitz", 50000, 20000, seed=5)
+    check(c, "dodis", 8219, 8219, seed=6)
+    c.close()
