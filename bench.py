@@ -266,6 +266,38 @@ def run_batched(log, count=4096, reps=3):
             "per_block_Mbit_s": round(sum_m / (t_u * 1e-3) / 1e6, 1), "outputs_identical": bool(same)}
 
 
+def run_paper_shapes(log, reps=2):
+    """The paper's QKD privacy-amplification shapes (NEXT row f3)."""
+    import numpy as np
+    import torch
+
+    import paper_2402_09481_amd as P
+    import workloads as W
+    out = {}
+    ctx = P.Context(0)
+    for name, make in (("qkd_toeplitz", W.qkd_toeplitz), ("qkd_circulant", lambda: W.qkd_circulant(P.next_na_set))):
+        log("paper shapes: %s" % name)
+        job = make()
+        x = torch.from_numpy(job.x.view(np.int64)).cuda()
+        y = torch.from_numpy(job.y.view(np.int64)).cuda()
+        z = torch.empty(P.words(job.m), dtype=torch.int64, device="cuda")
+        ctx.extract(job.kind, x, y, job.n, job.m, z=z, sync=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.extract(job.kind, x, y, job.n, job.m, z=z)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"kind": job.kind, "n": job.n, "m": job.m, "ms": round(ms, 3),
+                     "output_Mbit_s": round(job.m / (ms * 1e-3) / 1e6, 2),
+                     "input_Mbit_s": round(job.n / (ms * 1e-3) / 1e6, 2)}
+        del x, y, z
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +307,7 @@ def main():
     ap.add_argument("--batched", action="store_true", help="also run the 4096-block batched comparison")
     ap.add_argument("--serving", action="store_true", help="also run a short serving sweep")
     ap.add_argument("--warm", action="store_true", help="also time the headline with the seed transform cached")
+    ap.add_argument("--paper-shapes", action="store_true", help="also time the paper's QKD extraction shapes")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run a plain device copy of this many GiB first (reference for byte counters)")
     args = ap.parse_args()
@@ -300,6 +333,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(job, args.cpu_seconds)
     if args.batched:
         out["batched"] = run_batched(log)
+    if args.paper_shapes:
+        out["paper_shapes"] = run_paper_shapes(log)
     if args.serving:
         from paper_2402_09481_amd import serve
         out["serving"] = serve.bench(log=log)

@@ -82,3 +82,15 @@ def test_null_context_calls(lib):
     assert lib.ext_mem_stats(None, None, None, None) == -1
     assert lib.ext_profile(None, 1) == -1
     assert lib.ext_tune_set(None, 32, 20, 2, None) == -1
+
+
+def test_paper_qrng_shapes_exceed_the_largest_transform(lib):
+    """The QRNG example (n = 6.5e9) needs a transform longer than 2^32 (the 64-bit
+    field's limit): rejected as too large; the QKD shapes fit 2^31."""
+    import workloads as W
+    assert lib.ext_plan_length(0, W.QRNG_N, W.QRNG_M, None) == 0
+    n_adj = oracle.closest_na(W.QRNG_N + 1)
+    assert lib.ext_plan_length(1, n_adj - 1, 500_000_000, None) == 0
+    assert lib.ext_plan_length(0, W.QKD_N, W.QKD_M, None) == 1 << 31
+    n_in, m = W.qkd_circulant_shape(oracle.next_na)
+    assert lib.ext_plan_length(1, n_in, m, None) == 1 << 31

@@ -128,6 +128,47 @@ def toeplitz_large(seed: int = BASE_SEED + 2, n: int = 1 << 30, m: int = 1 << 29
     return Job("toeplitz", n, m, x, y, "paper")
 
 
+# The paper's QKD privacy-amplification example (section "Cryptomite for privacy
+# amplification in QKD"): n = 1.738e9 raw-key bits, m = 41,378,264 output bits with
+# the Toeplitz extractor; the improved variant uses Circulant with the input padded
+# to n_adj - 1 bits, n_adj the next prime >= n + 1 with primitive root 2, a weak seed
+# of min-entropy rate r = 0.99 and error 1e-10, and m = floor(k1 + k2 - n_adj +
+# 2 log2(eps)) with k1 = m_toeplitz - 2 log2(eps) and k2 = r n_adj.
+QKD_N = 1_738_000_000
+QKD_M = 41_378_264
+QKD_EPS = 1e-10
+QKD_RATE = 0.99
+
+# The QRNG example (section "Cryptomite for randomness extraction in (Q)RNG"):
+QRNG_N = 6_500_000_000
+QRNG_M = 581_294_933
+
+
+def qkd_toeplitz(seed: int = BASE_SEED + 6) -> Job:
+    g = rng(seed)
+    x = bernoulli_bits(g, QKD_N, 0.5)
+    y = bernoulli_bits(g, QKD_N + QKD_M - 1, 0.5)
+    return Job("toeplitz", QKD_N, QKD_M, x, y, "paper")
+
+
+def qkd_circulant_shape(next_na):
+    """(n_in, m) of the improved QKD extraction; next_na comes from the caller."""
+    n_adj = int(next_na(QKD_N + 1))
+    k1 = QKD_M - 2 * math.log2(QKD_EPS)
+    k2 = QKD_RATE * n_adj
+    m = int(math.floor(k1 + k2 - n_adj + 2 * math.log2(QKD_EPS)))
+    return n_adj - 1, m
+
+
+def qkd_circulant(next_na, seed: int = BASE_SEED + 7) -> Job:
+    n_in, m = qkd_circulant_shape(next_na)
+    g = rng(seed)
+    x = np.zeros(nwords(n_in), dtype="<u8")
+    x[: nwords(QKD_N)] = bernoulli_bits(g, QKD_N, 0.5)  # raw key padded with zeros to n_in bits
+    y = bernoulli_bits(g, n_in + 1, 0.5)
+    return Job("circulant", n_in, m, x, y)
+
+
 def batch_params(count: int = 4096, seed: int = BASE_SEED + 3, next_na=None,
                  log_lo: float = 10.0, log_hi: float = 22.0):
     """Block parameters for the batched workload, drawn from one master stream.
