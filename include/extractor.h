@@ -50,8 +50,8 @@ extern "C" {
 #define EXT_ENOTNA (-2)      /* length must be a prime with 2 as a primitive root */
 #define EXT_EDEGENERATE (-3) /* Dodis et al.: x is all zeros or all ones */
 #define EXT_ENOMEM (-4)      /* workspace does not fit the context's HBM budget */
-#define EXT_ETOOLARGE (-5)   /* the transform length would exceed 2^32 */
-#define EXT_EDEVICE (-6)     /* a HIP runtime call failed */
+#define EXT_ETOOLARGE (-5)   /* the transform length would exceed 2^32 (Von Neumann: n beyond EXT_VN_MAX_BITS) */
+#define EXT_EDEVICE (-6)     /* a HIP runtime call failed (Von Neumann: also a device-side wait that ran out) */
 
 /* ---- flags ---------------------------------------------------------- */
 /* Toeplitz seed order. PAPER (default): the matrix of eq. (toep) in the
@@ -114,10 +114,29 @@ int extract_circulant(ext_ctx *ctx, const uint64_t *x, uint64_t n_in, const uint
 int extract_dodis(ext_ctx *ctx, const uint64_t *x, const uint64_t *y, uint64_t n, uint64_t m, uint64_t *z,
                   uint32_t flags, int32_t *status, void *stream);
 
+/* Von Neumann extractor (section "Von Neumann": for every pair
+ * (x_{2j}, x_{2j+1}), j < floor(n/2), in order of j, output x_{2j} when the two
+ * bits differ and nothing when they are equal; Alg. 3).
+ *   x: n bits, 2 <= n <= EXT_VN_MAX_BITS (EXT_EINVAL below, EXT_ETOOLARGE
+ *   above); a trailing odd bit belongs to no pair.
+ *   z: z_words >= ceil(floor(n/2) / 64) words (the longest possible output;
+ *   EXT_EINVAL otherwise). Words of z below ceil(m/64) are written, the bits
+ *   of the last one beyond m as 0; later words are not touched.
+ *   m_out: device or host-pinned uint64 (not NULL), receives the output length
+ *   m, which depends on the data (about p(1-p)n for i.i.d. bits of bias p).
+ *   When no pair differs (Alg. 3's error case) m = 0 and the status is
+ *   EXT_EDEGENERATE; written to *status (device or host-pinned, nullable) and
+ *   returned with EXT_SYNC. flags: EXT_SYNC only. */
+#define EXT_VN_MAX_BITS (((uint64_t)1) << 40)
+int extract_von_neumann(ext_ctx *ctx, const uint64_t *x, uint64_t n, uint64_t *z, uint64_t z_words, uint64_t *m_out,
+                        uint32_t flags, int32_t *status, void *stream);
+
 /* ---- batched entry point -------------------------------------------- */
 #define EXT_KIND_TOEPLITZ 0
 #define EXT_KIND_CIRCULANT 1
 #define EXT_KIND_DODIS 2
+/* ext_workspace_bytes only (extract_batch rejects it): the Von Neumann call */
+#define EXT_KIND_VON_NEUMANN 3
 
 typedef struct ext_job {
     int32_t kind;          /* EXT_KIND_* */
@@ -153,7 +172,8 @@ int extract_batch_unbatched(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t 
 /* ---- sizes, memory, utilities --------------------------------------- */
 
 /* Device workspace bytes one extraction of this shape takes from the pool
- * (0 if the shape is invalid). kind: EXT_KIND_*; n as for the calls. */
+ * (0 if the shape is invalid). kind: EXT_KIND_*; n as for the calls (m is
+ * ignored for EXT_KIND_VON_NEUMANN). */
 size_t ext_workspace_bytes(int32_t kind, uint64_t n, uint64_t m);
 
 /* Transform length L and field (32 or 64 = word bits) chosen for a shape; 0 on error. */

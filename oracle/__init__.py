@@ -1,4 +1,5 @@
-"""Oracle for the convolution extractors — TEST INFRASTRUCTURE ONLY.
+"""Oracle for the convolution extractors and the Von Neumann extractor — TEST
+INFRASTRUCTURE ONLY.
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may import
 this package. It shares no code with the GPU library (``paper_2402_09481_amd``)
@@ -12,8 +13,11 @@ paper: Toeplitz needs 1 <= m <= n; Circulant needs n = n_in + 1 prime with
 primitive root 2 and 1 <= m <= n - 1 (full row rank bound of the Circulant
 proof); Dodis et al. needs n prime with primitive root 2, 1 <= m <= n and
 x not all-zero and not all-one (precondition stated with the Dodis
-implementation). On a failed precondition the functions return the error code
-and no output.
+implementation). Von Neumann needs n >= 2 (one pair) and reports EDEGENERATE
+when no pair differs, the error case of its implementation (Alg. 3), which
+prints no return value: here the output is returned and the error raised only
+for an empty output. On a failed precondition the functions return the error
+code and no output.
 """
 from __future__ import annotations
 
@@ -55,6 +59,8 @@ def _load():
         lib.oracle_toeplitz_rows.argtypes = [u64p, u64, u64p, u64, ctypes.c_int, u64, u64, u64p]
         lib.oracle_dodis_rows.argtypes = [u64p, u64p, u64, u64, u64, u64p]
         lib.oracle_circulant_rows.argtypes = [u64p, u64, u64p, u64, u64, u64p]
+        lib.oracle_von_neumann_bits.argtypes = [u64p, u64, u64p]
+        lib.oracle_von_neumann_bits.restype = ctypes.c_uint64
         for f in (lib.oracle_toeplitz_bits, lib.oracle_dodis_bits, lib.oracle_circulant_bits,
                   lib.oracle_toeplitz_rows, lib.oracle_dodis_rows, lib.oracle_circulant_rows):
             f.restype = None
@@ -247,3 +253,20 @@ def extract(kind: str, x, y, n: int, m: int, seed_order: str = "paper", packed: 
     if kind == "circulant":
         return OK, circulant_rows(x, y, n, m, 0, m)
     return OK, dodis_rows(x, y, n, m, 0, m)
+
+
+# ------------------------------------------------------------------ Von Neumann
+
+def von_neumann(x, n: int):
+    """(code, z, m): the Von Neumann output (section "Von Neumann", Alg. 3) as
+    ceil(m/64) packed words and its length m. code EINVAL for n < 2;
+    EDEGENERATE (with z empty and m = 0) when no pair of bits differs."""
+    n = int(n)
+    if n < 2:
+        return EINVAL, None, 0
+    out = np.zeros(_nw(n // 2) + 1, np.uint64)
+    xx = _masked(x, n)
+    m = int(_load().oracle_von_neumann_bits(_p(xx), n, _p(out)))
+    if m == 0:
+        return EDEGENERATE, out[:0], 0
+    return OK, out[: _nw(m)], m

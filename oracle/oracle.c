@@ -1,5 +1,6 @@
 /*
- * Oracle for the Toeplitz, Circulant and Dodis et al. extractors.
+ * Oracle for the Toeplitz, Circulant and Dodis et al. extractors, and for the
+ * Von Neumann extractor.
  *
  * TEST INFRASTRUCTURE ONLY. Nothing in the product library links, calls or
  * reads this file; only the tests, the smoke check and the CPU baseline of the
@@ -19,6 +20,10 @@
  *   Dodis et al. (Sec. "Dodis and Circulant implementation", the full matrix
  *   and the R(x) convolution form):
  *       z_i = XOR_{j<n} x_{(j-i) mod n} & y_j
+ *
+ *   Von Neumann (Sec. "Von Neumann", the definition of output bit j, and
+ *   Alg. 3): for the pairs (x_{2j}, x_{2j+1}), j < floor(n/2), in order of j,
+ *       emit x_{2j} when x_{2j} != x_{2j+1}, nothing otherwise.
  *
  * Bit layout: bit i of a string is (w[i >> 6] >> (i & 63)) & 1.
  * Preconditions (lengths, primality, degenerate inputs) are checked by the
@@ -180,4 +185,17 @@ void oracle_circulant_rows(const uint64_t *x, uint64_t n_in, const uint64_t *y, 
     for (uint64_t j = 0; j < n_in; ++j) put(xp, j, bit(x, j));
     circ_rows_packed(xp, y, n, i0, cnt, out);
     free(xp);
+}
+
+/* ------------------------------------------------------------ Von Neumann
+ * Pair by pair, as the definition reads: the output is appended to while the
+ * pairs are walked in order. Returns the number of output bits m; out must have
+ * room for floor(n/2) bits and is written only at bits < m. */
+uint64_t oracle_von_neumann_bits(const uint64_t *x, uint64_t n, uint64_t *out) {
+    uint64_t m = 0;
+    for (uint64_t j = 0; j < n / 2; ++j) {
+        int a = bit(x, 2 * j), b = bit(x, 2 * j + 1);
+        if (a != b) put(out, m++, a);
+    }
+    return m;
 }

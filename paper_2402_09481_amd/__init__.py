@@ -1,4 +1,5 @@
-"""MI355X (gfx950) convolution extractors: Toeplitz, Circulant, Dodis et al.
+"""MI355X (gfx950) randomness extractors: Toeplitz, Circulant, Dodis et al.
+(convolution extractors) and Von Neumann.
 
 Python binding of libextractor.so (``include/extractor.h``). It only
 marshals arguments: every step of an extraction runs in the library's HIP
@@ -9,7 +10,8 @@ Bit strings are packed little-endian uint64 words (bit i at
 The classes follow the paper's interface, ``Toeplitz(n_1, m).extract(x, y)``
 (section "Cryptomite for privacy amplification in QKD"), with
 ``Circulant(n_1, m)`` taking the input length n_1 (n_1 + 1 must be a prime with
-2 as a primitive root) and ``Dodis(n, m)``.
+2 as a primitive root), ``Dodis(n, m)`` and ``VonNeumann(n)``, whose output
+length depends on the data.
 """
 from __future__ import annotations
 
@@ -21,7 +23,7 @@ from ._lib import (EXT_EDEGENERATE, EXT_EINVAL, EXT_ENOMEM, EXT_ENOTNA, EXT_ETOO
                    EXT_KIND_CIRCULANT, EXT_KIND_DODIS, EXT_KIND_TOEPLITZ, EXT_SEED_LINEAR, EXT_SEED_PAPER,
                    EXT_SYNC, ExtError, ExtJob, KINDS)
 
-__all__ = ["Context", "Toeplitz", "Circulant", "Dodis", "extract", "extract_batch", "is_na_prime", "next_na_set",
+__all__ = ["Context", "Toeplitz", "Circulant", "Dodis", "VonNeumann", "extract", "extract_batch", "is_na_prime", "next_na_set",
            "closest_na_set", "words", "ExtError", "ExtJob", "default_context"]
 
 
@@ -148,6 +150,30 @@ class Context:
             raise ExtError(rc, "extract_" + kind)
         return z if check else (rc, z)
 
+    def von_neumann(self, x, n: int, z=None, m_out=None, sync: bool = False, status=None, stream=None,
+                    check: bool = True):
+        """Von Neumann extractor (section "Von Neumann", Alg. 3) on the n bits of x.
+        z: words(n // 2) words or more (allocated if None); m_out: one-element int64
+        device tensor for the output length (allocated if None). Returns (z, m_out), with
+        m_out read back as an int when sync=True; the first words(m) words of z carry
+        the output. No differing pair: EXT_EDEGENERATE (raised when check and sync)."""
+        import torch
+        if z is None:
+            z = torch.empty(max(1, words(int(n) // 2)), dtype=torch.int64, device=x.device)
+        if m_out is None:
+            m_out = torch.zeros(1, dtype=torch.int64, device=x.device)
+        if m_out.element_size() != 8 or not m_out.is_cuda:
+            raise TypeError("m_out must be a 64-bit GPU tensor")
+        st = ctypes.c_void_p(status.data_ptr()) if status is not None else None
+        rc = self._lib.extract_von_neumann(self.handle, _ptr(x), int(n), _ptr(z), int(z.numel()),
+                                           ctypes.c_void_p(m_out.data_ptr()), EXT_SYNC if sync else 0, st,
+                                           _stream_handle(stream))
+        if check and rc != EXT_OK:
+            raise ExtError(rc, "extract_von_neumann")
+        if sync:
+            m_out = int(m_out.item())
+        return (z, m_out) if check else (rc, z, m_out)
+
     def tune_set(self, word_bits: int, lg: int, levels):
         """Override the plan for transform length 2^lg: levels = [] for one workgroup per
         job, a list of pass sizes (log2) otherwise, None to drop the override."""
@@ -241,3 +267,14 @@ class Circulant(_Extractor):
 class Dodis(_Extractor):
     """Dodis(n, m): x and y have n bits (n prime with primitive root 2)."""
     kind = "dodis"
+
+
+class VonNeumann:
+    """VonNeumann(n): x has n bits; extract returns (z, m) with m output bits."""
+
+    def __init__(self, n: int, context: Context | None = None):
+        self.n, self.context = int(n), context
+
+    def extract(self, x, z=None, stream=None):
+        ctx = self.context or default_context(x.device.index or 0)
+        return ctx.von_neumann(x, self.n, z=z, sync=True, stream=stream)

@@ -28,8 +28,11 @@ EXT_SEED_CACHED = 8
 EXT_KIND_TOEPLITZ = 0
 EXT_KIND_CIRCULANT = 1
 EXT_KIND_DODIS = 2
+EXT_KIND_VON_NEUMANN = 3
+EXT_VN_MAX_BITS = 1 << 40
 
-KINDS = {"toeplitz": EXT_KIND_TOEPLITZ, "circulant": EXT_KIND_CIRCULANT, "dodis": EXT_KIND_DODIS}
+KINDS = {"toeplitz": EXT_KIND_TOEPLITZ, "circulant": EXT_KIND_CIRCULANT, "dodis": EXT_KIND_DODIS,
+         "von_neumann": EXT_KIND_VON_NEUMANN}
 
 # every symbol declared in include/extractor.h
 SYMBOLS = [
@@ -37,7 +40,7 @@ SYMBOLS = [
     "extract_batch", "extract_batch_unbatched", "ext_workspace_bytes", "ext_plan_length",
     "ext_mem_stats", "ext_trim", "ext_is_na_prime", "ext_next_na", "ext_closest_na",
     "ext_strerror", "ext_version", "ext_profile", "ext_profile_read",
-    "ext_tune_set", "ext_tune_get", "ext_tune_save", "ext_seed_cache_clear",
+    "ext_tune_set", "ext_tune_get", "ext_tune_save", "ext_seed_cache_clear", "extract_von_neumann",
 ]
 
 
@@ -83,6 +86,8 @@ def load() -> ctypes.CDLL:
     lib.extract_dodis.argtypes = [vp, vp, vp, u64, u64, vp, u32, vp, vp]
     for f in (lib.extract_toeplitz, lib.extract_circulant, lib.extract_dodis):
         f.restype = ctypes.c_int
+    lib.extract_von_neumann.argtypes = [vp, vp, u64, vp, u64, vp, u32, vp, vp]
+    lib.extract_von_neumann.restype = ctypes.c_int
     lib.extract_batch.argtypes = [vp, ctypes.POINTER(ExtJob), sz, u32, vp]
     lib.extract_batch.restype = ctypes.c_int
     lib.extract_batch_unbatched.argtypes = [vp, ctypes.POINTER(ExtJob), sz, u32, vp]

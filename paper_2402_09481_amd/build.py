@@ -1,7 +1,8 @@
 """Build libextractor.so (gfx950) in-tree with hipcc.
 
-The kernel file is compiled as several parts in parallel (one per group of
-template instantiations), then linked with the C-ABI into one shared
+The transform kernel file is compiled as several parts in parallel (one per
+group of template instantiations), the Von Neumann kernels and the C-ABI as
+one object each, then linked with the C-ABI into one shared
 library next to this file. Always rebuilds when called."""
 from __future__ import annotations
 
@@ -40,8 +41,9 @@ def build(verbose: bool = False) -> str:
     for part in range(NTT_PARTS):
         obj = os.path.join(BUILD, "ntt_part%d.o" % part)
         jobs.append(([HIPCC] + FLAGS + ["-DNTT_PART=%d" % part, "-c", os.path.join(CSRC, "ntt.hip"), "-o", obj], obj))
-    obj = os.path.join(BUILD, "abi.o")
-    jobs.append(([HIPCC] + FLAGS + ["-c", os.path.join(CSRC, "abi.cpp"), "-o", obj], obj))
+    for src in ("vonneumann.hip", "abi.cpp"):
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        jobs.append(([HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj], obj))
     workers = min(len(jobs), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(workers) as ex:
         for out in ex.map(lambda j: _run(j[0]), jobs):

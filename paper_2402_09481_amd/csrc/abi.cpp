@@ -849,6 +849,7 @@ uint64_t ext_closest_na(uint64_t v) {
 size_t ext_workspace_bytes(int32_t kind, uint64_t n, uint64_t m) {
     Shape s;
     Plan p;
+    if (kind == EXT_KIND_VON_NEUMANN) return (n >= 2 && n <= EXT_VN_MAX_BITS) ? align256(vn_workspace_bytes(n)) : 0;
     if (shape_of(kind, n, m, s) != EXT_OK) return 0;
     if (make_plan(s.Lmin, 0, p) != EXT_OK) return 0;
     return workspace_layout(p).total;
@@ -1068,6 +1069,65 @@ int extract_dodis(ext_ctx *ctx, const uint64_t *x, const uint64_t *y, uint64_t n
                   uint32_t flags, int32_t *status, void *stream) {
     if (flags & EXT_SEED_LINEAR) return EXT_EINVAL;
     return extract_one(ctx, EXT_KIND_DODIS, x, n, y, m, z, flags, status, (hipStream_t)stream);
+}
+
+int extract_von_neumann(ext_ctx *c, const uint64_t *x, uint64_t n, uint64_t *z, uint64_t z_words, uint64_t *m_out,
+                        uint32_t flags, int32_t *status, void *stream) {
+    if (!c || !x || !z || !m_out) return EXT_EINVAL;
+    if (flags & ~EXT_SYNC) return EXT_EINVAL;
+    if (n < 2) return EXT_EINVAL;
+    if (n > EXT_VN_MAX_BITS) return EXT_ETOOLARGE;
+    if (z_words < words(n / 2) || z_words > (uint64_t(1) << 58)) return EXT_EINVAL;
+    const size_t zb = z_words * 8;
+    if (overlaps(z, zb, x, words(n) * 8) || overlaps(z, zb, m_out, 8) || (status && overlaps(z, zb, status, 4)))
+        return EXT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(c->device) != hipSuccess) return EXT_EDEVICE;
+    Lease lease;
+    int rc = pool_acquire(c, vn_workspace_bytes(n), s, lease);
+    if (rc != EXT_OK) return rc;
+    int32_t *st = status;
+    int32_t *mine = nullptr;
+    if ((flags & EXT_SYNC) && !st) {
+        if (!(mine = take_pinned_status(c))) {
+            pool_release(c, lease, s);
+            return EXT_EDEVICE;
+        }
+        *mine = 0;
+        st = mine;
+    }
+    const VnWork w = vn_work(lease.ptr, n);
+    Tracer tr(c, s, false);
+    tr.begin();
+    hipError_t e = launch_vn_zero(w, n, s);
+    tr.end("vn_zero");
+    if (e == hipSuccess) {
+        tr.begin();
+        e = launch_vn_main(x, n, z, z_words, w, s);
+        tr.end("vn_main");
+    }
+    if (e == hipSuccess) {
+        tr.begin();
+        e = launch_vn_fix(w, n, z, z_words, m_out, st, s);
+        tr.end("vn_fix");
+    }
+    pool_release(c, lease, s);
+    if (e != hipSuccess) {
+        if (mine) give_pinned_status(c, mine);
+        return EXT_EDEVICE;
+    }
+    rc = EXT_OK;
+    if (flags & EXT_SYNC) {
+        if (hipStreamSynchronize(s) != hipSuccess) rc = EXT_EDEVICE;
+        else {
+            int32_t v = 0;
+            if (mine) v = *mine;
+            else if (hipMemcpy(&v, st, sizeof(v), hipMemcpyDefault) != hipSuccess) v = EXT_EDEVICE;
+            rc = v;
+        }
+        if (mine) give_pinned_status(c, mine);
+    }
+    return rc;
 }
 
 int extract_batch_unbatched(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t flags, void *stream) {

@@ -120,4 +120,22 @@ hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint32_t njobs, cons
 // Dodis degenerate-input check (writes flags).
 hipError_t launch_degen(uint32_t njobs, const JobDev *jobs, const JobDev *one, hipStream_t s);
 
+// Von Neumann compaction (vonneumann.hip). Workspace of one call: the
+// look-back state of every tile (flag in bits 62-63, value below), the partial
+// first and last output word of every tile, counter[0] = tile ticket,
+// counter[1] = error flag.
+struct VnWork {
+    uint64_t *state;
+    uint64_t *pf;
+    uint64_t *pl;
+    uint32_t *counter;
+};
+uint64_t vn_tiles(uint64_t n);
+size_t vn_workspace_bytes(uint64_t n);
+VnWork vn_work(char *ws, uint64_t n);
+hipError_t launch_vn_zero(const VnWork &w, uint64_t n, hipStream_t s);
+hipError_t launch_vn_main(const uint64_t *x, uint64_t n, uint64_t *z, uint64_t zcap, const VnWork &w, hipStream_t s);
+hipError_t launch_vn_fix(const VnWork &w, uint64_t n, uint64_t *z, uint64_t zcap, uint64_t *m_out, int32_t *status,
+                         hipStream_t s);
+
 }  // namespace ext

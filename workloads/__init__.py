@@ -247,3 +247,39 @@ def serving_pool(seed: int = BASE_SEED + 5):
     pool = bernoulli_bits(g, SERVE_POOL_BITS, 0.5)
     seeds = [bernoulli_bits(g, SERVE_SEED_BITS, 0.5) for _ in range(SERVE_SEEDS)]
     return pool, seeds
+
+
+# ------------------------------------------------------------------ Von Neumann inputs
+
+# The Von Neumann input of the paper's throughput figure: input min-entropy fixed to
+# half the length, which for i.i.d. bits means max(p, 1 - p) = 2^(-1/2).
+VN_P = 1.0 - 2.0 ** -0.5
+VN_PAPER_N = 500_000_000    # the largest input length of the throughput figure
+VN_LARGE_N = 1 << 33        # 1 GiB of input bits: one HBM-scale call
+
+
+def von_neumann_input(n: int, p: float = VN_P, seed: int = BASE_SEED + 8) -> np.ndarray:
+    """n i.i.d. bits with P(bit = 1) = p (host, PCG64)."""
+    return bernoulli_bits(rng(seed), n, p)
+
+
+def bernoulli_bits_device(n: int, p: float, seed: int, device="cuda", chunk_words: int = 1 << 21):
+    """n i.i.d. bits with P(bit = 1) = p, packed as above, drawn on the device by
+    torch's generator seeded with `seed` (for inputs too large to draw on the host
+    in reasonable time). Returns an int64 tensor of nwords(n) words."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    W = nwords(n)
+    out = torch.empty(W, dtype=torch.int64, device=device)
+    weights = (2 ** torch.arange(8, device=device)).to(torch.uint8)
+    for w0 in range(0, W, chunk_words):
+        w1 = min(W, w0 + chunk_words)
+        bits = torch.rand((w1 - w0, 8, 8), generator=gen, device=device) < p
+        by = (bits.to(torch.uint8) * weights).sum(dim=2, dtype=torch.uint8)  # (words, 8) bytes
+        out[w0:w1] = by.contiguous().view(torch.int64).view(-1)
+        del bits, by
+    r = n & 63
+    if r:
+        out[W - 1] &= (1 << r) - 1
+    return out
