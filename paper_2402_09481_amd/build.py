@@ -25,6 +25,10 @@ FLAGS = [
     "-Wno-unused-value", "-Wno-unused-result",
 ]
 NTT_PARTS = 5
+# The Von Neumann kernel takes its next tile's ticket with one lane and reads it
+# a whole tile later; LLVM's atomic optimizer would broadcast the result right
+# away and so wait for the atomic's round trip on every tile.
+VN_FLAGS = ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 
 
 def _run(cmd):
@@ -41,9 +45,9 @@ def build(verbose: bool = False) -> str:
     for part in range(NTT_PARTS):
         obj = os.path.join(BUILD, "ntt_part%d.o" % part)
         jobs.append(([HIPCC] + FLAGS + ["-DNTT_PART=%d" % part, "-c", os.path.join(CSRC, "ntt.hip"), "-o", obj], obj))
-    for src in ("vonneumann.hip", "abi.cpp"):
+    for src, extra in (("vonneumann.hip", VN_FLAGS), ("abi.cpp", [])):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-        jobs.append(([HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj], obj))
+        jobs.append(([HIPCC] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj], obj))
     workers = min(len(jobs), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(workers) as ex:
         for out in ex.map(lambda j: _run(j[0]), jobs):
