@@ -71,6 +71,8 @@ def kernel_bytes(label: str, L: int, w: int, n: int, N: int, m: int) -> int:
 PROFILE_BYTES = os.path.join(ROOT, "profiles", "toeplitz_n2p30_hbm_bytes.md")
 KERNEL_SOURCES = ["paper_2402_09481_amd/csrc/ntt.hip", "paper_2402_09481_amd/csrc/field.h",
                   "paper_2402_09481_amd/csrc/kernels.h"]
+PROFILE_VN = os.path.join(ROOT, "profiles", "von_neumann_kernel_trace_and_bytes.md")
+VN_SOURCES = ["paper_2402_09481_amd/csrc/vonneumann.hip", "paper_2402_09481_amd/csrc/kernels.h"]
 
 
 def profiled_traffic(label: str):
@@ -93,6 +95,25 @@ def profiled_traffic(label: str):
     field = "FGL" if "u64" in label else "FBB"
     name = "k_%s<%s, %s, %s>" % (kind, field, f["lgr"], f["mode"])
     e = blob.get("per_launch", {}).get(name)
+    return None if e is None else e["read_bytes"] + e["write_bytes"]
+
+
+def profiled_vn_traffic(n: int):
+    """Calibrated HBM bytes (read + write) of one Von Neumann main-kernel launch at
+    input length n, from the committed summary; None if absent or taken on other
+    kernel sources."""
+    import hashlib
+    try:
+        text = open(PROFILE_VN).read()
+        blob = json.loads(text.rsplit("```json", 1)[1].split("```", 1)[0])  # the last block
+    except (OSError, IndexError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for fn in VN_SOURCES:
+        h.update(open(os.path.join(ROOT, fn), "rb").read())
+    if h.hexdigest() != blob.get("kernel_sources_sha256"):
+        return None
+    e = blob.get("per_launch", {}).get(str(n))
     return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
@@ -298,6 +319,66 @@ def run_paper_shapes(log, reps=2):
     return out
 
 
+def run_von_neumann(log, reps=10, oracle_bits=1 << 27):
+    """The Von Neumann extractor (NEXT row f4(b)): i.i.d. input with min-entropy half
+    its length (the paper's throughput-figure setting), at the figure's largest input
+    length and at 2^33 bits. Input and output bytes against the HBM roofline; the
+    oracle timed on a sample for context."""
+    import time
+
+    import numpy as np
+    import torch
+
+    import paper_2402_09481_amd as P
+    import workloads as W
+    ctx = P.Context(0)
+    out = {"p_one": round(W.VN_P, 6), "shapes": []}
+    for n in (W.VN_PAPER_N, W.VN_LARGE_N):
+        log("von neumann: n=%d" % n)
+        x = W.bernoulli_bits_device(n, W.VN_P, W.BASE_SEED + 10)
+        z = torch.empty(P.words(n // 2), dtype=torch.int64, device="cuda")
+        mo = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            ctx.von_neumann(x, n, z=z, m_out=mo)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.von_neumann(x, n, z=z, m_out=mo)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        per = {}
+        for name, t in ctx.profile_read():
+            per.setdefault(name, []).append(t)
+        ctx.profile(False)
+        m = int(mo.item())
+        main_ms = sum(per["vn_main"]) / len(per["vn_main"])
+        algo = n // 8 + m // 8  # input read once, output written once
+        out["shapes"].append({
+            "n": n, "m": m, "ms_per_call": round(ms, 4),
+            "input_Gbit_s": round(n / (ms * 1e-3) / 1e9, 2),
+            "output_Mbit_s": round(m / (ms * 1e-3) / 1e6, 1),
+            "kernels_ms": {k: round(sum(v) / len(v), 4) for k, v in per.items()},
+            "roofline": {"bound": "hbm", "kernel": "vn_main", "achieved": round(algo / (main_ms * 1e-3) / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(algo / (main_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "algo_bytes": algo,
+                         "traffic": profiled_vn_traffic(n)},
+        })
+        del x, z
+    ctx.close()
+    torch.cuda.empty_cache()
+    import oracle
+    xs = W.von_neumann_input(oracle_bits, seed=W.BASE_SEED + 11)
+    t0 = time.perf_counter()
+    code, oz, om = oracle.von_neumann(xs, oracle_bits)
+    dt = time.perf_counter() - t0
+    out["cpu_baseline"] = {"value": round(om / dt / 1e6, 2), "unit": "Mbit/s (output)", "cores": 1, "kind": "oracle",
+                           "sample": "%d i.i.d. input bits, p = %.4f" % (oracle_bits, W.VN_P)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +389,7 @@ def main():
     ap.add_argument("--serving", action="store_true", help="also run a short serving sweep")
     ap.add_argument("--warm", action="store_true", help="also time the headline with the seed transform cached")
     ap.add_argument("--paper-shapes", action="store_true", help="also time the paper's QKD extraction shapes")
+    ap.add_argument("--von-neumann", action="store_true", help="also time the Von Neumann extractor")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run a plain device copy of this many GiB first (reference for byte counters)")
     args = ap.parse_args()
@@ -335,6 +417,8 @@ def main():
         out["batched"] = run_batched(log)
     if args.paper_shapes:
         out["paper_shapes"] = run_paper_shapes(log)
+    if args.von_neumann:
+        out["von_neumann"] = run_von_neumann(log)
     if args.serving:
         from paper_2402_09481_amd import serve
         out["serving"] = serve.bench(log=log)

@@ -94,3 +94,16 @@ def test_paper_qrng_shapes_exceed_the_largest_transform(lib):
     assert lib.ext_plan_length(0, W.QKD_N, W.QKD_M, None) == 1 << 31
     n_in, m = W.qkd_circulant_shape(oracle.next_na)
     assert lib.ext_plan_length(1, n_in, m, None) == 1 << 31
+
+
+def test_von_neumann_host_surface(lib):
+    # workspace: look-back state, first and last partial word per tile of 2^18 input bits
+    assert lib.ext_workspace_bytes(3, 1, 0) == 0
+    assert lib.ext_workspace_bytes(3, (1 << 40) + 2, 0) == 0
+    tiles = lambda n: -(-((n & ~1) // 64 + (1 if (n & ~1) % 64 else 0)) // 4096)  # noqa: E731
+    for n in (2, 1000, 1 << 18, (1 << 18) + 1, 5 * 10 ** 8, 1 << 33):
+        want = (3 * 8 * tiles(n) + 256 + 255) // 256 * 256
+        assert lib.ext_workspace_bytes(3, n, 0) == want, n
+    # the convolution kinds reject nothing they did before; Von Neumann is not a plan
+    assert lib.ext_plan_length(3, 1000, 10, None) == 0
+    assert lib.extract_von_neumann(None, None, 1000, None, 100, None, 0, None, None) == -1
