@@ -92,7 +92,7 @@ def profiled_traffic(label: str):
         return None
     kind = label.split("[")[0]
     f = dict(kv.split("=") for kv in label.split("[")[1].rstrip("]").split(",")[1:])
-    field = "FGL" if "u64" in label else "FBB"
+    field = "FGL" if "[u64" in label else "FP0" if "[p0" in label else "FBB"
     name = "k_%s<%s, %s, %s>" % (kind, field, f["lgr"], f["mode"])
     e = blob.get("per_launch", {}).get(name)
     return None if e is None else e["read_bytes"] + e["write_bytes"]

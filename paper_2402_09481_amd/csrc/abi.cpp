@@ -197,17 +197,24 @@ bool split_levels(int field, int lg, Plan &p) {
     return false;
 }
 
-// force: 0 = automatic, 1 = 15*2^27+1, 2 = Goldilocks (testing aid)
+// The field of a plan: 15*2^27+1 up to its 2^27, then 3*2^30+1 (32-bit words
+// as well) up to 2^30, then Goldilocks. Every coefficient is at most the input
+// length n <= L, below all three primes.
+// force: 0 = automatic, 1 = 15*2^27+1, 2 = Goldilocks, 3 = 3*2^30+1 (testing aid)
 int make_plan(uint64_t Lmin, int force, Plan &p) {
     p = Plan();
     p.lg = std::max(MIN_LG, ceil_log2(Lmin));
     if (p.lg > 32) return EXT_ETOOLARGE;
-    p.field = p.lg <= FBB::LGMAX ? FIELD_BB : FIELD_GL;
+    p.field = p.lg <= FBB::LGMAX ? FIELD_BB : p.lg <= FP0::LGMAX ? FIELD_P0 : FIELD_GL;
     if (force == 1) {
         if (p.lg > FBB::LGMAX) return EXT_ETOOLARGE;
         p.field = FIELD_BB;
     } else if (force == 2) {
         p.field = FIELD_GL;
+        p.lg = std::max(p.lg, 2 * MIN_LEVEL_LG);
+    } else if (force == 3) {
+        if (p.lg > FP0::LGMAX) return EXT_ETOOLARGE;
+        p.field = FIELD_P0;
         p.lg = std::max(p.lg, 2 * MIN_LEVEL_LG);
     }
     if (p.field == FIELD_BB && p.lg <= max_small_lg()) {
@@ -229,7 +236,7 @@ Layout workspace_layout(const Plan &p) {
     Layout l;
     if (p.small) return l;
     const size_t L = size_t(1) << p.lg;
-    const size_t w = p.field == FIELD_BB ? 4 : 8;
+    const size_t w = p.field == FIELD_GL ? 8 : 4;
     const size_t bits = align256((L / 64 + 2) * 8);
     l.a = 0;
     l.b = align256(L * w);
@@ -310,13 +317,16 @@ int validate(const Shape &s, const uint64_t *x, const uint64_t *y, const uint64_
     return check_primes(s);
 }
 
-// Pointwise constant: BB folds L^-1 and two Montgomery factors, GL just L^-1.
+// Pointwise constant: the 32-bit fields fold L^-1 and two Montgomery factors
+// (mont(mont(u, v), K) = u v L^-1), Goldilocks just L^-1.
+template <class F>
+uint64_t mont_K(int lg) {
+    const uint32_t Linv = F::powmod(F::powmod(2, lg), F::P - 2);
+    return F::mulmod(F::mulmod(Linv, F::R_MOD_P), F::R_MOD_P);
+}
 uint64_t pointwise_K(const Plan &p) {
-    if (p.field == FIELD_BB) {
-        uint32_t Linv = FBB::powmod(FBB::powmod(2, p.lg), FBB::P - 2);
-        uint32_t R = FBB::R_MOD_P;
-        return FBB::mulmod(FBB::mulmod(Linv, R), R);
-    }
+    if (p.field == FIELD_BB) return mont_K<FBB>(p.lg);
+    if (p.field == FIELD_P0) return mont_K<FP0>(p.lg);
     return FGL::powmod(FGL::powmod(2, p.lg), FGL::P - 2);
 }
 
@@ -378,8 +388,8 @@ struct ext_ctx {
     size_t leased = 0;
     std::vector<Block> free_blocks;
     std::mutex mu;
-    Tables tb[2];
-    void *tb_mem[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    Tables tb[NFIELDS];
+    void *tb_mem[NFIELDS][3] = {};
     int force_field = 0;
     std::map<int, Plan> tuned;  // key: field * 64 + lg
     hipStream_t capture_stream = nullptr;
@@ -417,6 +427,13 @@ struct ext_ctx {
 };
 
 namespace {
+
+// The field a tuning entry refers to: 32-bit words are 15*2^27+1 up to its
+// 2^27 and 3*2^30+1 above; -1 if no field has that length.
+int tune_field(int word_bits, int lg) {
+    if (word_bits == 64) return lg <= FGL::LGMAX ? FIELD_GL : -1;
+    return lg <= FBB::LGMAX ? FIELD_BB : lg <= FP0::LGMAX ? FIELD_P0 : -1;
+}
 
 bool valid_plan(const Plan &p) {
     if (p.small) return p.field == FIELD_BB && p.lg >= MIN_LG && p.lg <= max_small_lg() && p.nlev == 0;
@@ -544,11 +561,12 @@ struct Tracer {
     }
 };
 
-// "<kind>[<word>,lgr=<log2 transform size>,mode=<pass mode>,arr=<0: input, 1: seed>]"
+// "<kind>[<field>,lgr=<log2 transform size>,mode=<pass mode>,arr=<0: input, 1: seed>]"
+// field: u32 = 15*2^27+1, p0 = 3*2^30+1 (32-bit words), u64 = Goldilocks
+const char *field_tag(int field) { return field == FIELD_BB ? "u32" : field == FIELD_P0 ? "p0" : "u64"; }
 std::string pass_label(const char *what, int field, int lgr, int mode, int which = 0) {
     char b[112];
-    snprintf(b, sizeof b, "%s[%s,lgr=%d,mode=%d,arr=%d]", what, field == FIELD_BB ? "u32" : "u64", lgr, mode,
-             which);
+    snprintf(b, sizeof b, "%s[%s,lgr=%d,mode=%d,arr=%d]", what, field_tag(field), lgr, mode, which);
     return b;
 }
 
@@ -690,7 +708,7 @@ ext_ctx::SeedEntry *seed_entry(ext_ctx *c, const Shape &sh, const Plan &p, const
     char key[160];
     snprintf(key, sizeof key, "%p:%d:%llu:%llu:%u:%d:%d", (const void *)y, sh.kind, (unsigned long long)sh.n,
              (unsigned long long)sh.m, flags & EXT_SEED_LINEAR, p.field, p.lg);
-    const size_t bytes = (size_t(1) << p.lg) * (p.field == FIELD_BB ? 4 : 8);
+    const size_t bytes = (size_t(1) << p.lg) * (p.field == FIELD_GL ? 8 : 4);
     std::unique_lock<std::mutex> g(c->mu);
     auto it = c->seeds.find(key);
     if (it != c->seeds.end()) {
@@ -860,7 +878,7 @@ uint64_t ext_plan_length(int32_t kind, uint64_t n, uint64_t m, int32_t *word_bit
     Plan p;
     if (shape_of(kind, n, m, s) != EXT_OK) return 0;
     if (make_plan(s.Lmin, 0, p) != EXT_OK) return 0;
-    if (word_bits) *word_bits = p.field == FIELD_BB ? 32 : 64;
+    if (word_bits) *word_bits = p.field == FIELD_GL ? 64 : 32;
     return uint64_t(1) << p.lg;
 }
 
@@ -878,9 +896,10 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
         return EXT_EDEVICE;
     }
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)freeb);
-    const char *ff = getenv("EXT_FORCE_FIELD");  // testing aid: "bb" or "gl"
+    const char *ff = getenv("EXT_FORCE_FIELD");  // testing aid: "bb", "gl" or "p0"
     if (ff && !strcmp(ff, "gl")) c->force_field = 2;
     if (ff && !strcmp(ff, "bb")) c->force_field = 1;
+    if (ff && !strcmp(ff, "p0")) c->force_field = 3;
     // twiddle tables
     auto upload = [&](int f, int k, const void *src, size_t bytes) -> bool {
         void *d = nullptr;
@@ -907,12 +926,20 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
         ok = ok && upload(FIELD_GL, 0, lo.data(), lo.size() * 8) && upload(FIELD_GL, 1, hi.data(), hi.size() * 8) &&
              upload(FIELD_GL, 2, in.data(), in.size() * 8);
     }
+    {
+        using F = FP0;
+        auto lo = table_pow<F>(F::WMAX, size_t(1) << 16);
+        auto hi = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << 16), size_t(1) << (F::LGMAX - 16));
+        auto in = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << (F::LGMAX - TWIN_LG)), size_t(1) << TWIN_LG);
+        ok = ok && upload(FIELD_P0, 0, lo.data(), lo.size() * 4) && upload(FIELD_P0, 1, hi.data(), hi.size() * 4) &&
+             upload(FIELD_P0, 2, in.data(), in.size() * 4);
+    }
     if (ok) ok = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         ext_destroy(c);
         return EXT_EDEVICE;
     }
-    for (int f = 0; f < 2; ++f) c->tb[f] = Tables{c->tb_mem[f][0], c->tb_mem[f][1], c->tb_mem[f][2]};
+    for (int f = 0; f < NFIELDS; ++f) c->tb[f] = Tables{c->tb_mem[f][0], c->tb_mem[f][1], c->tb_mem[f][2]};
     if (tune_path) {
         // lines "<word_bits> <lg> <nlev> <lgr...>"; anything unparsable or unsupported is skipped
         if (FILE *f = fopen(tune_path, "r")) {
@@ -944,7 +971,7 @@ void ext_destroy(ext_ctx *c) {
         if (kv.second.desc_host) hipHostFree(kv.second.desc_host);
         if (kv.second.done) hipEventDestroy(kv.second.done);
     }
-    for (int f = 0; f < 2; ++f)
+    for (int f = 0; f < NFIELDS; ++f)
         for (int k = 0; k < 3; ++k)
             if (c->tb_mem[f][k]) hipFree(c->tb_mem[f][k]);
     for (auto p : c->pinned_status) hipHostFree(p);
@@ -960,7 +987,8 @@ void ext_destroy(ext_ctx *c) {
 
 int ext_tune_set(ext_ctx *c, int word_bits, int lg, int nlev, const int *lgr) {
     if (!c || (word_bits != 32 && word_bits != 64) || lg < MIN_LG || lg > 32) return EXT_EINVAL;
-    const int field = word_bits == 32 ? FIELD_BB : FIELD_GL;
+    const int field = tune_field(word_bits, lg);
+    if (field < 0) return EXT_EINVAL;
     std::lock_guard<std::mutex> g(c->mu);
     if (nlev < 0) {
         c->tuned.erase(field * 64 + lg);
@@ -982,7 +1010,8 @@ int ext_tune_set(ext_ctx *c, int word_bits, int lg, int nlev, const int *lgr) {
 
 int ext_tune_get(ext_ctx *c, int word_bits, int lg, int *nlev, int *lgr) {
     if (!c || (word_bits != 32 && word_bits != 64) || lg < MIN_LG || lg > 32) return EXT_EINVAL;
-    const int field = word_bits == 32 ? FIELD_BB : FIELD_GL;
+    const int field = tune_field(word_bits, lg);
+    if (field < 0) return EXT_EINVAL;
     Plan p;
     {
         std::lock_guard<std::mutex> g(c->mu);
@@ -990,7 +1019,7 @@ int ext_tune_get(ext_ctx *c, int word_bits, int lg, int *nlev, int *lgr) {
         if (it != c->tuned.end()) p = it->second;
     }
     if (p.lg == 0) {
-        const int rc = make_plan(uint64_t(1) << lg, field == FIELD_GL ? 2 : 1, p);
+        const int rc = make_plan(uint64_t(1) << lg, field == FIELD_GL ? 2 : field == FIELD_P0 ? 3 : 1, p);
         if (rc != EXT_OK) return rc;
     }
     if (nlev) *nlev = p.small ? 0 : p.nlev;
@@ -1007,7 +1036,7 @@ int ext_tune_save(ext_ctx *c, const char *path) {
     fprintf(f, "# word_bits lg nlev lgr...  (nlev 0: one workgroup per job)\n");
     for (auto &kv : c->tuned) {
         const Plan &p = kv.second;
-        fprintf(f, "%d %d %d", p.field == FIELD_BB ? 32 : 64, p.lg, p.small ? 0 : p.nlev);
+        fprintf(f, "%d %d %d", p.field == FIELD_GL ? 64 : 32, p.lg, p.small ? 0 : p.nlev);
         for (int i = 0; i < (p.small ? 0 : p.nlev); ++i) fprintf(f, " %d", p.lgr[i]);
         fprintf(f, "\n");
     }

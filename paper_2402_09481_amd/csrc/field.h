@@ -11,12 +11,16 @@
 //        canonical in [0, p); products use Montgomery multiplication with
 //        R = 2^32, and twiddle tables hold Montgomery forms w*R mod p, so that
 //        mont(a, w*R) = a*w mod p.
+//   FP0: p = 3 * 2^30 + 1 (> 2^31, < 2^32), 32-bit words, L <= 2^30. As FBB
+//        (canonical values, Montgomery products with R = 2^32, Montgomery-form
+//        twiddles), but a + b of two canonical values can pass 2^32, so add
+//        and sub use the carry / borrow instead of the unsigned-min trick.
 //   FGL: p = 2^64 - 2^32 + 1, 64-bit words, L <= 2^32. Values are any 64-bit
 //        representative (< 2^64) of their class; only canon() returns the
 //        representative in [0, p). 2^64 = 2^32 - 1 (mod p) and 2^96 = -1 (mod p)
 //        give a multiply-free reduction of 128-bit products.
 //
-// Both fields use one fixed primitive root of unity w_max of order 2^LGMAX;
+// Every field uses one fixed primitive root of unity w_max of order 2^LGMAX;
 // every transform of length L uses w_L = w_max^(2^LGMAX / L), so that all
 // sub-transforms of a multi-pass transform agree on their roots.
 #pragma once
@@ -67,6 +71,61 @@ struct FBB {
     __device__ static inline uint32_t mul_root(uint32_t x);
 
     // host/compile-time helpers
+    __host__ __device__ static constexpr uint32_t mulmod(uint32_t a, uint32_t b) {
+        return (uint32_t)((uint64_t)a * b % P);
+    }
+    __host__ __device__ static constexpr uint32_t powmod(uint32_t a, uint64_t e) {
+        uint32_t r = 1;
+        while (e) {
+            if (e & 1) r = mulmod(r, a);
+            a = mulmod(a, a);
+            e >>= 1;
+        }
+        return r;
+    }
+    __host__ __device__ static constexpr uint32_t to_tw(uint32_t w) {  // Montgomery form
+        return (uint32_t)(((uint64_t)w << 32) % P);
+    }
+};
+
+// ------------------------------------------------------------ 3 * 2^30 + 1
+struct FP0 {
+    using T = uint32_t;
+    static constexpr uint32_t P = 0xC0000001u;
+    static constexpr uint32_t PINV = 1073741825u;  // P^-1 mod 2^32
+    static constexpr int LGMAX = 30;
+    static constexpr uint32_t WMAX = 125u;         // 5^3: order 2^30 (5 generates the group)
+    static constexpr uint32_t R_MOD_P = 1073741823u; // 2^32 mod P (Montgomery form of 1)
+    static constexpr int WORD_BITS = 32;
+
+    // a, b in [0, P): a + b < 2P may carry out of 32 bits; the result is
+    // a + b - P when it carried or reached P, else a + b.
+    __device__ static inline uint32_t add(uint32_t a, uint32_t b) {
+        uint32_t s;
+        const bool c = __builtin_add_overflow(a, b, &s);
+        return (c || s >= P) ? s - P : s;
+    }
+    __device__ static inline uint32_t sub(uint32_t a, uint32_t b) {
+        const uint32_t d = a - b;
+        return a < b ? d + P : d;
+    }
+    // Montgomery product a*b*2^-32 mod P for a, b < P (signed variant, as FBB):
+    // hi - mulhi(q, P) lies in (-P, P) since hi = (a b) >> 32 < P.
+    __device__ static inline uint32_t mont(uint32_t a, uint32_t b) {
+        const uint32_t lo = a * b;
+        const uint32_t hi = __umulhi(a, b);
+        const uint32_t q = lo * PINV;
+        const uint32_t m = __umulhi(q, P);
+        return sub(hi, m);
+    }
+    __device__ static inline uint32_t mul_tw(uint32_t a, uint32_t tw) { return mont(a, tw); }
+    __device__ static inline uint32_t tw_combine(uint32_t hi, uint32_t lo) { return mont(hi, lo); }
+    __device__ static inline uint32_t canon(uint32_t a) { return a; }
+    __device__ static inline uint32_t from_bit(uint32_t b) { return b; }
+    __device__ static inline uint32_t as_b(uint32_t v) { return v; }
+    template <int RAD, int K>
+    __device__ static inline uint32_t mul_root(uint32_t x);
+
     __host__ __device__ static constexpr uint32_t mulmod(uint32_t a, uint32_t b) {
         return (uint32_t)((uint64_t)a * b % P);
     }
@@ -191,6 +250,12 @@ template <int RAD, int K>
 __device__ inline uint32_t FBB::mul_root(uint32_t x) {
     constexpr uint32_t w = FBB::powmod(FBB::powmod(FBB::WMAX, (uint64_t(1) << FBB::LGMAX) / RAD), K);
     return mont(x, FBB::to_tw(w));
+}
+
+template <int RAD, int K>
+__device__ inline uint32_t FP0::mul_root(uint32_t x) {
+    constexpr uint32_t w = FP0::powmod(FP0::powmod(FP0::WMAX, (uint64_t(1) << FP0::LGMAX) / RAD), K);
+    return mont(x, FP0::to_tw(w));
 }
 
 // Compile-time table of the RAD-th roots of unity w_RAD^k (k < RAD) in twiddle form.

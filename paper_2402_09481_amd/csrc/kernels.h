@@ -64,7 +64,8 @@ struct Tables {
 constexpr int TWIN_LG = 14;
 
 // Field selector for the launchers.
-enum FieldId : int { FIELD_BB = 0, FIELD_GL = 1 };
+enum FieldId : int { FIELD_BB = 0, FIELD_GL = 1, FIELD_P0 = 2 };
+constexpr int NFIELDS = 3;
 
 // Tile geometry (host copy of the kernels' compile-time choices).
 struct Geometry {

@@ -41,7 +41,7 @@
 #include "field.h"
 #include "kernels.h"
 
-// The file is compiled once per part (NTT_PART = 0..4) so that the template
+// The file is compiled once per part (NTT_PART = 0..6) so that the template
 // instantiations build in parallel; without NTT_PART everything is built.
 #ifndef NTT_PART
 #define NTT_PART -1
@@ -757,8 +757,10 @@ constexpr int SMALL_MAX = 14;
 
 hipError_t launch_strided_bb(const PassLaunch &p, const Tables &t, hipStream_t s);
 hipError_t launch_strided_gl(const PassLaunch &p, const Tables &t, hipStream_t s);
+hipError_t launch_strided_p0(const PassLaunch &p, const Tables &t, hipStream_t s);
 hipError_t launch_contig_bb(const PassLaunch &p, const Tables &t, hipStream_t s);
 hipError_t launch_contig_gl(const PassLaunch &p, const Tables &t, hipStream_t s);
+hipError_t launch_contig_p0(const PassLaunch &p, const Tables &t, hipStream_t s);
 
 #if NTT_HAS(0)
 hipError_t launch_strided_bb(const PassLaunch &p, const Tables &t, hipStream_t s) {
@@ -819,9 +821,40 @@ hipError_t launch_contig_gl(const PassLaunch &p, const Tables &t, hipStream_t s)
 }
 #endif
 
+#if NTT_HAS(5)
+hipError_t launch_strided_p0(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    KArgs ka = make_args(p, t);
+    switch (p.lgr) {
+        case 7: return strided_one<FP0, 7>(p, ka, s);
+        case 8: return strided_one<FP0, 8>(p, ka, s);
+        case 9: return strided_one<FP0, 9>(p, ka, s);
+        case 10: return strided_one<FP0, 10>(p, ka, s);
+    }
+    return hipErrorInvalidValue;
+}
+#endif
+
+#if NTT_HAS(6)
+hipError_t launch_contig_p0(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    KArgs ka = make_args(p, t);
+    switch (p.lgr) {
+        case 7: return contig_one<FP0, 7>(p, ka, s);
+        case 8: return contig_one<FP0, 8>(p, ka, s);
+        case 9: return contig_one<FP0, 9>(p, ka, s);
+        case 10: return contig_one<FP0, 10>(p, ka, s);
+        case 11: return contig_one<FP0, 11>(p, ka, s);
+        case 12: return contig_one<FP0, 12>(p, ka, s);
+        case 13: return contig_one<FP0, 13>(p, ka, s);
+        case 14: return contig_one<FP0, 14>(p, ka, s);
+    }
+    return hipErrorInvalidValue;
+}
+#endif
+
 #if NTT_HAS(4)
-int max_strided_lg(int field) { return field == FIELD_BB ? BB_STRIDED_MAX : GL_STRIDED_MAX; }
-int max_contig_lg(int field) { return field == FIELD_BB ? BB_CONTIG_MAX : GL_CONTIG_MAX; }
+// the 32-bit fields share tile sizes
+int max_strided_lg(int field) { return field == FIELD_GL ? GL_STRIDED_MAX : BB_STRIDED_MAX; }
+int max_contig_lg(int field) { return field == FIELD_GL ? GL_CONTIG_MAX : BB_CONTIG_MAX; }
 int max_small_lg() { return SMALL_MAX; }
 
 template <class F>
@@ -842,14 +875,28 @@ static Geometry geo_c(int lgr) {
     }
     return Geometry{0, 0};
 }
-Geometry strided_geometry(int field, int lgr) { return field == FIELD_BB ? geo_s<FBB>(lgr) : geo_s<FGL>(lgr); }
-Geometry contig_geometry(int field, int lgr) { return field == FIELD_BB ? geo_c<FBB>(lgr) : geo_c<FGL>(lgr); }
+Geometry strided_geometry(int field, int lgr) {
+    return field == FIELD_GL ? geo_s<FGL>(lgr) : field == FIELD_P0 ? geo_s<FP0>(lgr) : geo_s<FBB>(lgr);
+}
+Geometry contig_geometry(int field, int lgr) {
+    return field == FIELD_GL ? geo_c<FGL>(lgr) : field == FIELD_P0 ? geo_c<FP0>(lgr) : geo_c<FBB>(lgr);
+}
 
 hipError_t launch_strided(const PassLaunch &p, const Tables &t, hipStream_t s) {
-    return p.field == FIELD_BB ? launch_strided_bb(p, t, s) : launch_strided_gl(p, t, s);
+    switch (p.field) {
+        case FIELD_BB: return launch_strided_bb(p, t, s);
+        case FIELD_GL: return launch_strided_gl(p, t, s);
+        case FIELD_P0: return launch_strided_p0(p, t, s);
+    }
+    return hipErrorInvalidValue;
 }
 hipError_t launch_contig(const PassLaunch &p, const Tables &t, hipStream_t s) {
-    return p.field == FIELD_BB ? launch_contig_bb(p, t, s) : launch_contig_gl(p, t, s);
+    switch (p.field) {
+        case FIELD_BB: return launch_contig_bb(p, t, s);
+        case FIELD_GL: return launch_contig_gl(p, t, s);
+        case FIELD_P0: return launch_contig_p0(p, t, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int LG>
@@ -909,7 +956,7 @@ hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint32_t njobs, cons
     JobDev o;
     if (one) o = *one;
     else std::memset(&o, 0, sizeof(o));
-    const int C = field == FIELD_BB ? 32 : 16;
+    const int C = field == FIELD_GL ? 16 : 32;  // strided tile columns: 128-byte rows
     dim3 grid((unsigned)((R + 63) / 64), (unsigned)((S / C + 63) / 64), njobs);
     if (C == 16)
         hipLaunchKernelGGL(k_ptrans<16>, grid, dim3(256), 0, s, jobs, o, R, S);

@@ -32,6 +32,20 @@ def ctx_gl():
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx_p0():
+    """A context that runs every shape on 3*2^30+1 (the 32-bit field of transforms
+    from 2^28 to 2^30), multi-pass, at small sizes."""
+    import paper_2402_09481_amd as P
+    os.environ["EXT_FORCE_FIELD"] = "p0"
+    try:
+        c = P.Context(0)
+    finally:
+        del os.environ["EXT_FORCE_FIELD"]
+    yield c
+    c.close()
+
+
 def seed_len(kind, n, m):
     return {"toeplitz": n + m - 1, "circulant": n + 1, "dodis": n}[kind]
 
@@ -107,6 +121,15 @@ def test_dodis_workload(ctx):
                                       ("dodis", 8219, 8219), ("circulant", 16420, 8000)])
 def test_64bit_field_path(ctx_gl, kind, n, m):
     run_case(ctx_gl, kind, n, m, "paper", seed=3 * n + m)
+
+
+@pytest.mark.parametrize("kind,n,m", [("toeplitz", 9000, 7000), ("toeplitz", 100000, 50000), ("toeplitz", 129, 64),
+                                      ("toeplitz", 1 << 20, 1 << 19), ("dodis", 8219, 8219),
+                                      ("circulant", 16420, 8000)])
+def test_p0_field_path(ctx_p0, kind, n, m):
+    run_case(ctx_p0, kind, n, m, "paper", seed=5 * n + m)
+    if kind == "toeplitz":
+        run_case(ctx_p0, kind, n, m, "linear", seed=7 * n + m)
 
 
 def test_dodis_degenerate_inputs(ctx):
