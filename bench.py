@@ -63,8 +63,8 @@ def kernel_bytes(label: str, L: int, w: int, n: int, N: int, m: int) -> int:
         if mode == 3:
             return Lw + m // 8
         return 2 * Lw
-    if kind == "contig":
-        return 3 * Lw if mode == 1 else 2 * Lw
+    if kind == "contig":  # mode 2: the two-piece fused pass (4 arrays in, 1 out)
+        return 5 * Lw if mode == 2 else 3 * Lw if mode == 1 else 2 * Lw
     return 0
 
 
@@ -153,8 +153,9 @@ def run_headline(args):
     ctx = P.Context(0)
     stream = torch.cuda.current_stream()
     log("warmup x%d" % args.warmup)
+    # the configuration's transform: one of length 2^31 over the 64-bit prime
     for _ in range(args.warmup):
-        ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream)
+        ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream, single_transform=True)
     torch.cuda.synchronize()
     ctx.profile(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -162,7 +163,7 @@ def run_headline(args):
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
-        ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream)
+        ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream, single_transform=True)
     e1.record(stream)
     torch.cuda.synchronize()
     ctx.profile(False)
@@ -215,12 +216,13 @@ def run_headline(args):
     if args.warm:
         # NEXT row f1: the same extraction with the seed's transform cached (a hit
         # skips one of the three transforms; 7 L w algorithmic bytes)
-        ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream, cache_seed=True)
+        ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream, cache_seed=True, single_transform=True)
         torch.cuda.synchronize()
         w0, w1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         w0.record(stream)
         for _ in range(args.steps):
-            ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream, cache_seed=True)
+            ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream, cache_seed=True,
+                        single_transform=True)
         w1.record(stream)
         torch.cuda.synchronize()
         wms = w0.elapsed_time(w1) / args.steps
@@ -229,10 +231,52 @@ def run_headline(args):
                                    "unit": "Mbit/s", "algo_bytes": wbytes,
                                    "achieved_GBs": round(wbytes / (wms * 1e-3) / 1e9, 1)}
         ctx.seed_cache_clear()
+    if args.two_piece:
+        out["two_piece"] = run_two_piece(ctx, job, x, y, z, stream, args, ms)
     ctx.close()
     del x, y, z
     torch.cuda.empty_cache()
     return out, job
+
+
+def run_two_piece(ctx, job, x, y, z, stream, args, single_ms):
+    """NEXT row f2: the same extraction with the library's default plan for this
+    shape, the two-piece schedule (input halves of 2^29 bits, transforms of 2^30 over
+    3*2^30+1 in 32-bit words, products added before one inverse). Same output bits
+    (checked here against the single transform); a different arithmetic path, so it is
+    reported beside the headline, not as it."""
+    import torch
+    z1 = z.clone()
+    ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(z, z1))
+    ctx.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    ms = e0.elapsed_time(e1) / args.steps
+    L, w = 1 << 30, 4
+    a = job.n // 2
+    agg = {}
+    for label, t in ctx.profile_read():
+        e = agg.setdefault(label, [0.0, 0])
+        e[0] += t
+        e[1] += 1
+    kernels, total_bytes = [], 0
+    for label, (tot, cnt) in agg.items():
+        b = kernel_bytes(label, L, w, a, a + job.m - 1, job.m)
+        total_bytes += b * cnt // args.steps
+        kernels.append({"kernel": label, "launches_per_step": cnt // args.steps, "avg_ms": round(tot / cnt, 4),
+                        "algo_bytes": b, "achieved_GBs": round(b / (tot / cnt * 1e-3) / 1e9, 1)})
+    kernels.sort(key=lambda k: -k["avg_ms"] * k["launches_per_step"])
+    return {"ms_per_step": round(ms, 3), "value": round(job.m / (ms * 1e-3) / 1e6, 2), "unit": "Mbit/s",
+            "speedup_vs_single_transform": round(single_ms / ms, 2), "same_bits_as_single_transform": same,
+            "transform_length": L, "word_bytes": w, "algo_bytes_per_step": total_bytes,
+            "achieved_GBs": round(total_bytes / (ms * 1e-3) / 1e9, 1), "kernels": kernels}
 
 
 def run_batched(log, count=4096, reps=3):
@@ -390,6 +434,8 @@ def main():
     ap.add_argument("--warm", action="store_true", help="also time the headline with the seed transform cached")
     ap.add_argument("--paper-shapes", action="store_true", help="also time the paper's QKD extraction shapes")
     ap.add_argument("--von-neumann", action="store_true", help="also time the Von Neumann extractor")
+    ap.add_argument("--two-piece", action="store_true",
+                    help="also time the headline shape with the default two-piece plan")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run a plain device copy of this many GiB first (reference for byte counters)")
     args = ap.parse_args()

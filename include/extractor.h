@@ -73,8 +73,18 @@ extern "C" {
  * shape (kind, n, m, seed order), so the caller must not change the seed bits
  * at that address while they are cached (ext_seed_cache_clear drops them).
  * A hit skips one of the three transforms. Sizes that run in one workgroup
- * ignore the flag. */
+ * and the two-piece schedule (see EXT_SINGLE_TRANSFORM) ignore the flag. */
 #define EXT_SEED_CACHED 8u
+/* Single calls: compute the extraction as one transform even where the
+ * two-piece schedule applies. By default a Toeplitz extraction whose single
+ * transform would need the 64-bit field (n + m - 1 > 2^30) while halves of the
+ * input fit transforms of at most 2^30 runs as two pieces over 3*2^30+1: the
+ * input split at a = ceil(n/2) rounded up to whole words, each half extracted
+ * with its own seed window (the sum defining z_i split at j = a), the two
+ * products added in the transform domain before one inverse — same bits,
+ * 32-bit arithmetic. This flag keeps the one transform of nextpow2(n+m-1) over
+ * 2^64 - 2^32 + 1. */
+#define EXT_SINGLE_TRANSFORM 16u
 
 typedef struct ext_ctx ext_ctx;
 
@@ -92,7 +102,8 @@ void ext_destroy(ext_ctx *ctx);
  * embedding into a circulant, eq. toeplitz-embed and Alg. 2).
  *   x: n bits (the weak input), y: n+m-1 bits (the seed), z: m bits.
  *   Requires 1 <= m <= n. z_i = XOR_{j<n} toep(y)[i][j] x_j over GF(2).
- *   flags: EXT_SEED_PAPER | EXT_SEED_LINEAR, optionally | EXT_SYNC. */
+ *   flags: EXT_SEED_PAPER | EXT_SEED_LINEAR, optionally | EXT_SYNC,
+ *   EXT_SEED_CACHED, EXT_SINGLE_TRANSFORM. */
 int extract_toeplitz(ext_ctx *ctx, const uint64_t *x, uint64_t n, const uint64_t *y, uint64_t m,
                      uint64_t *z, uint32_t flags, int32_t *status, void *stream);
 
@@ -176,7 +187,9 @@ int extract_batch_unbatched(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t 
  * ignored for EXT_KIND_VON_NEUMANN). */
 size_t ext_workspace_bytes(int32_t kind, uint64_t n, uint64_t m);
 
-/* Transform length L and field (32 or 64 = word bits) chosen for a shape; 0 on error. */
+/* Transform length L and field (32 or 64 = word bits) chosen for a shape by
+ * default (for the two-piece schedule: the length of each piece's transforms);
+ * 0 on error. */
 uint64_t ext_plan_length(int32_t kind, uint64_t n, uint64_t m, int32_t *word_bits);
 
 /* Pool accounting: budget, bytes currently leased by in-flight calls, bytes

@@ -128,14 +128,16 @@ class Context:
 
     # -- raw calls (device tensors in, device tensor out) --------------------------------
     def extract(self, kind: str, x, y, n: int, m: int, z=None, seed_order: str = "paper", sync: bool = False,
-                status=None, stream=None, check: bool = True, cache_seed: bool = False) -> "object":
+                status=None, stream=None, check: bool = True, cache_seed: bool = False,
+                single_transform: bool = False) -> "object":
         """cache_seed: keep / reuse the seed's transform (the seed bits at y must not
-        change while cached; see seed_cache_clear)."""
+        change while cached; see seed_cache_clear). single_transform: no two-piece
+        split of large Toeplitz extractions (one transform over the 64-bit field)."""
         import torch
         if z is None:
             z = torch.empty(words(m), dtype=torch.int64, device=x.device)
         flags = (EXT_SEED_LINEAR if seed_order == "linear" else 0) | (EXT_SYNC if sync else 0) | \
-            (_lib.EXT_SEED_CACHED if cache_seed else 0)
+            (_lib.EXT_SEED_CACHED if cache_seed else 0) | (_lib.EXT_SINGLE_TRANSFORM if single_transform else 0)
         st = ctypes.c_void_p(status.data_ptr()) if status is not None else None
         s = _stream_handle(stream)
         if kind == "toeplitz":

@@ -24,6 +24,7 @@ EXT_SEED_LINEAR = 1
 EXT_SYNC = 2
 EXT_GRAPH = 4
 EXT_SEED_CACHED = 8
+EXT_SINGLE_TRANSFORM = 16
 
 EXT_KIND_TOEPLITZ = 0
 EXT_KIND_CIRCULANT = 1

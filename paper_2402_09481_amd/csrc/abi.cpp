@@ -164,6 +164,8 @@ struct Plan {
     bool small = false;
     int nlev = 0;
     int lgr[4] = {0, 0, 0, 0};
+    int pieces = 1;      // 2: the two-piece schedule (Toeplitz input split at `split` bits)
+    uint64_t split = 0;
 };
 
 constexpr int MIN_LEVEL_LG = 7;
@@ -227,20 +229,28 @@ int make_plan(uint64_t Lmin, int force, Plan &p) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t a = 0, b = 0, pb = 0, eb0 = 0, eb1 = 0, flags = 0, total = 0;
+    size_t a = 0, b = 0, a2 = 0, b2 = 0, pb = 0, eb0 = 0, eb1 = 0, flags = 0, total = 0;
 };
 
-// A and B (L words each), the packed parity and the two embedded inputs (L bits
-// each, plus a spare word), and the degenerate-check flags.
+// A and B (L words each; the two-piece schedule has a second pair A2, B2), the
+// packed parity and the two embedded inputs (L bits each, plus a spare word),
+// and the degenerate-check flags.
 Layout workspace_layout(const Plan &p) {
     Layout l;
     if (p.small) return l;
     const size_t L = size_t(1) << p.lg;
     const size_t w = p.field == FIELD_GL ? 8 : 4;
     const size_t bits = align256((L / 64 + 2) * 8);
+    const size_t arr = align256(L * w);
     l.a = 0;
-    l.b = align256(L * w);
-    l.pb = l.b + align256(L * w);
+    l.b = arr;
+    size_t off = 2 * arr;
+    if (p.pieces == 2) {
+        l.a2 = off;
+        l.b2 = off + arr;
+        off += 2 * arr;
+    }
+    l.pb = off;
     l.eb0 = l.pb + bits;
     l.eb1 = l.eb0 + bits;
     l.flags = l.eb1 + bits;
@@ -311,7 +321,7 @@ uint64_t seed_bits(const Shape &s) {
 
 int validate(const Shape &s, const uint64_t *x, const uint64_t *y, const uint64_t *z, uint32_t flags) {
     if (!x || !y || !z) return EXT_EINVAL;
-    if (flags & ~(EXT_SEED_LINEAR | EXT_SYNC | EXT_SEED_CACHED)) return EXT_EINVAL;
+    if (flags & ~(EXT_SEED_LINEAR | EXT_SYNC | EXT_SEED_CACHED | EXT_SINGLE_TRANSFORM)) return EXT_EINVAL;
     const size_t zb = words(s.m) * 8;
     if (overlaps(z, zb, x, words(s.n) * 8) || overlaps(z, zb, y, words(seed_bits(s)) * 8)) return EXT_EINVAL;
     return check_primes(s);
@@ -330,16 +340,22 @@ uint64_t pointwise_K(const Plan &p) {
     return FGL::powmod(FGL::powmod(2, p.lg), FGL::P - 2);
 }
 
+// piece: 0 for a single transform and for the first piece of the two-piece
+// schedule (which also points at the second piece's spectra), 1 for its second.
 JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint64_t *y, uint64_t *z, int32_t *status,
-                   uint32_t flags, char *ws) {
+                   uint32_t flags, char *ws, int piece = 0) {
     JobDev j;
     std::memset(&j, 0, sizeof(j));
     const Layout l = workspace_layout(p);
     if (ws) {
-        j.A = ws + l.a;
-        j.B = ws + l.b;
+        j.A = ws + (piece ? l.a2 : l.a);
+        j.B = ws + (piece ? l.b2 : l.b);
         j.pb = (uint64_t *)(ws + l.pb);
         j.S = j.A;
+        if (p.pieces == 2 && piece == 0) {
+            j.S2 = ws + l.a2;
+            j.T2 = ws + l.b2;
+        }
         j.eb[0] = (uint64_t *)(ws + l.eb0);
         j.eb[1] = (uint64_t *)(ws + l.eb1);
         j.flags = (uint32_t *)(ws + l.flags);
@@ -351,7 +367,17 @@ JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint6
     j.nfold = s.nfold;
     j.out_len = s.out_len;
     j.K = pointwise_K(p);
-    if (s.kind == EXT_KIND_TOEPLITZ) {
+    if (s.kind == EXT_KIND_TOEPLITZ && p.pieces == 2) {
+        // z_i = sum_j s_{i-j+n-1} x_j split at j = a: piece 0 is the Toeplitz
+        // extractor of x_0..x_{a-1} with the seed window s_{n-a} .., piece 1 that of
+        // x_a..x_{n-1} with the window s_0 .. (each window a_p + m - 1 bits long)
+        const uint64_t N = s.n + s.m - 1, a = p.split;
+        const uint64_t ap = piece ? s.n - a : a, off = piece ? 0 : s.n - a, Np = ap + s.m - 1;
+        const uint64_t rot = ((flags & EXT_SEED_LINEAR) ? off : off + s.m) % N;
+        j.ex = Emb{piece ? x + a / 64 : x, ap, 0, 0, 0, 0, EMB_PREFIX, 0};
+        j.ey = Emb{y, Np, ap - 1, Np, rot, N, EMB_SEED, 0};
+        j.degen_n = 0;
+    } else if (s.kind == EXT_KIND_TOEPLITZ) {
         const uint64_t N = s.n + s.m - 1;
         j.ex = Emb{x, s.n, 0, 0, 0, 0, EMB_PREFIX, 0};
         const uint64_t rot = (flags & EXT_SEED_LINEAR) ? 0 : (s.m % N);
@@ -454,6 +480,41 @@ int plan_for(ext_ctx *c, uint64_t Lmin, Plan &p) {
     std::lock_guard<std::mutex> g(c->mu);
     auto it = c->tuned.find(p.field * 64 + p.lg);
     if (it != c->tuned.end()) p = it->second;
+    return EXT_OK;
+}
+
+// Two-piece schedule for Toeplitz shapes beyond one transform of 3*2^30+1: the
+// input is split at a = ceil(n/2) rounded up to whole words, and each half is a
+// Toeplitz extraction with its own seed window of a_p + m - 1 bits, so both run
+// as transforms of length nextpow2(a + m - 1) over 3*2^30+1 (every coefficient
+// of the two convolutions together is at most n < 3*2^30+1). Their products are
+// added in the transform domain before one inverse.
+constexpr uint64_t TWO_PIECE_MIN_N = 128;
+uint64_t two_piece_split(uint64_t n) { return ((n + 1) / 2 + 63) & ~uint64_t(63); }
+
+// The plan for a shape: a single transform (plan_for), or the two-piece
+// schedule for a Toeplitz shape whose single transform would need the 64-bit
+// field while each piece fits 3*2^30+1 (unless the caller asks for one
+// transform). Forced-field contexts keep single transforms, except force 4
+// (testing aid: two pieces whenever n allows).
+int plan_shape(ext_ctx *c, const Shape &s, Plan &p, uint32_t flags = 0) {
+    const int force = c ? c->force_field : 0;
+    const bool can_split = s.kind == EXT_KIND_TOEPLITZ && !(flags & EXT_SINGLE_TRANSFORM) && s.n >= TWO_PIECE_MIN_N &&
+                           two_piece_split(s.n) + s.m - 1 <= (uint64_t(1) << FP0::LGMAX);
+    if (force == 4) {
+        if (!can_split) return make_plan(s.Lmin, 3, p);
+        const int rc = make_plan(two_piece_split(s.n) + s.m - 1, 3, p);
+        p.pieces = 2;
+        p.split = two_piece_split(s.n);
+        return rc;
+    }
+    const int rc = plan_for(c, s.Lmin, p);
+    if (rc != EXT_OK || force || p.field != FIELD_GL || !can_split) return rc;
+    Plan q;
+    if (plan_for(c, two_piece_split(s.n) + s.m - 1, q) != EXT_OK || q.field != FIELD_P0) return rc;
+    q.pieces = 2;
+    q.split = two_piece_split(s.n);
+    p = q;
     return EXT_OK;
 }
 
@@ -575,7 +636,10 @@ std::string pass_label(const char *what, int field, int lgr, int mode, int which
 // COLD: both transforms, product, inverse, parity. SEED_ONLY: the seed's full
 // forward transform into B (a seed-cache entry). WARM: the input's transform
 // fused with the cached seed spectrum S, inverse in A, parity.
-enum Phase { PH_COLD = 0, PH_SEED_ONLY = 1, PH_WARM = 2 };
+// FWD_BOTH: both operands' full forward transforms (the second piece of the
+// two-piece schedule); TWO: the first piece, whose fused pass adds the second
+// piece's product.
+enum Phase { PH_COLD = 0, PH_SEED_ONLY = 1, PH_WARM = 2, PH_FWD_BOTH = 3, PH_TWO = 4 };
 
 hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs_dev, const JobDev *one,
                    uint64_t max_m, bool any_degen, hipStream_t s, bool capturing = false, Phase ph = PH_COLD) {
@@ -623,7 +687,9 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         PassLaunch pl;
         pl.field = p.field;
         pl.lgr = lc;
-        pl.mode = (ph == PH_SEED_ONLY || (ph == PH_COLD && which == 0)) ? C_FWD : C_FUSED;
+        pl.mode = (ph == PH_SEED_ONLY || ph == PH_FWD_BOTH || ((ph == PH_COLD || ph == PH_TWO) && which == 0))
+                      ? C_FWD
+                      : ph == PH_TWO ? C_FUSED2 : C_FUSED;
         pl.which = which;
         pl.S = 0;
         pl.Mprev = 0;
@@ -637,7 +703,7 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         tr.end(pass_label("contig", p.field, pl.lgr, pl.mode, which));
         if (e != hipSuccess) return e;
     }
-    if (ph == PH_SEED_ONLY) return hipSuccess;
+    if (ph == PH_SEED_ONLY || ph == PH_FWD_BOTH) return hipSuccess;
     // inverse: strided levels backwards; level 0 writes packed parity
     std::vector<uint64_t> mp(p.nlev);
     uint64_t M = L;
@@ -765,7 +831,7 @@ int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint6
     if (rc) return rc;
     if ((rc = validate(sh, x, y, z, flags)) != EXT_OK) return rc;
     Plan p;
-    if ((rc = plan_for(c, sh.Lmin, p)) != EXT_OK) return rc;
+    if ((rc = plan_shape(c, sh, p, flags)) != EXT_OK) return rc;
     if (hipSetDevice(c->device) != hipSuccess) return EXT_EDEVICE;
     const Layout lay = workspace_layout(p);
     Lease lease;
@@ -783,8 +849,10 @@ int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint6
     }
     JobDev jd = make_jobdev(sh, p, x, y, z, st, flags, lease.ptr);
     hipError_t e = hipSuccess;
-    ext_ctx::SeedEntry *se =
-        (flags & EXT_SEED_CACHED) && !p.small ? seed_entry(c, sh, p, y, flags, s, jd, e) : nullptr;
+    // (the two-piece schedule does not use the seed cache)
+    ext_ctx::SeedEntry *se = (flags & EXT_SEED_CACHED) && !p.small && p.pieces == 1
+                                 ? seed_entry(c, sh, p, y, flags, s, jd, e)
+                                 : nullptr;
     if (se && e != hipSuccess) {
         std::lock_guard<std::mutex> g(c->mu);
         se->busy--;
@@ -796,6 +864,10 @@ int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint6
             if (e == hipSuccess) e = hipEventRecord(se->used, s);
             std::lock_guard<std::mutex> g(c->mu);
             se->busy--;
+        } else if (p.pieces == 2) {
+            const JobDev jd1 = make_jobdev(sh, p, x, y, z, st, flags, lease.ptr, 1);
+            e = enqueue(c, p, 1, nullptr, &jd1, sh.m, false, s, false, PH_FWD_BOTH);
+            if (e == hipSuccess) e = enqueue(c, p, 1, nullptr, &jd, sh.m, false, s, false, PH_TWO);
         } else {
             e = enqueue(c, p, 1, nullptr, &jd, sh.m, jd.degen_n != 0, s);
         }
@@ -869,7 +941,7 @@ size_t ext_workspace_bytes(int32_t kind, uint64_t n, uint64_t m) {
     Plan p;
     if (kind == EXT_KIND_VON_NEUMANN) return (n >= 2 && n <= EXT_VN_MAX_BITS) ? align256(vn_workspace_bytes(n)) : 0;
     if (shape_of(kind, n, m, s) != EXT_OK) return 0;
-    if (make_plan(s.Lmin, 0, p) != EXT_OK) return 0;
+    if (plan_shape(nullptr, s, p) != EXT_OK) return 0;
     return workspace_layout(p).total;
 }
 
@@ -877,7 +949,7 @@ uint64_t ext_plan_length(int32_t kind, uint64_t n, uint64_t m, int32_t *word_bit
     Shape s;
     Plan p;
     if (shape_of(kind, n, m, s) != EXT_OK) return 0;
-    if (make_plan(s.Lmin, 0, p) != EXT_OK) return 0;
+    if (plan_shape(nullptr, s, p) != EXT_OK) return 0;
     if (word_bits) *word_bits = p.field == FIELD_GL ? 64 : 32;
     return uint64_t(1) << p.lg;
 }
@@ -900,6 +972,7 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
     if (ff && !strcmp(ff, "gl")) c->force_field = 2;
     if (ff && !strcmp(ff, "bb")) c->force_field = 1;
     if (ff && !strcmp(ff, "p0")) c->force_field = 3;
+    if (ff && !strcmp(ff, "p0x2")) c->force_field = 4;  // two-piece schedule wherever it can run
     // twiddle tables
     auto upload = [&](int f, int k, const void *src, size_t bytes) -> bool {
         void *d = nullptr;

@@ -373,17 +373,21 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
     run_steps_from<F, Tl, false, 0>(v, lds, a.tb);
     constexpr int RADL = Ends<Tl, false>::RAD_LAST;
     constexpr int GPTL = EPT / RADL;
-    if constexpr (MODE == C_FUSED) {
+    if constexpr (MODE == C_FUSED || MODE == C_FUSED2) {
         static_assert(Ends<Tl, true>::RAD_FIRST == RADL, "register hand-over needs equal radices");
         const T K = (T)J.K;
+        const T *spec2 = (const T *)J.S2;
+        const T *seed2 = (const T *)J.T2;
 #pragma unroll
         for (int q = 0; q < GPTL; ++q) {
             int c, j;
             Tl::template coords<RADL>(q, c, j);
 #pragma unroll
             for (int t = 0; t < RADL; ++t) {
-                T x = spec[base + (uint64_t)c * R + j + t * (R / RADL)];
-                v[q * RADL + t] = F::mont(F::mont(v[q * RADL + t], x), K);
+                const uint64_t gi = base + (uint64_t)c * R + j + t * (R / RADL);
+                T prod = F::mont(v[q * RADL + t], spec[gi]);
+                if constexpr (MODE == C_FUSED2) prod = F::add(prod, F::as_b(F::mont(spec2[gi], seed2[gi])));
+                v[q * RADL + t] = F::mont(prod, K);
             }
         }
         __syncthreads();  // LDS is reused by the inverse steps
@@ -745,10 +749,17 @@ template <class F, int LGR>
 static hipError_t contig_one(const PassLaunch &p, const KArgs &ka, hipStream_t s) {
     using Tl = Tile<F, LGR, false>;
     dim3 grid((unsigned)p.tiles, p.njobs), block(Tl::NT);
-    if (p.mode == C_FUSED)
+    if (p.mode == C_FUSED2) {
+        // only the 32-bit field 3*2^30+1 runs the two-piece schedule
+        if constexpr (std::is_same<F, FP0>::value)
+            hipLaunchKernelGGL((k_contig<F, LGR, C_FUSED2>), grid, block, 0, s, ka);
+        else
+            return hipErrorInvalidValue;
+    } else if (p.mode == C_FUSED) {
         hipLaunchKernelGGL((k_contig<F, LGR, C_FUSED>), grid, block, 0, s, ka);
-    else
+    } else {
         hipLaunchKernelGGL((k_contig<F, LGR, C_FWD>), grid, block, 0, s, ka);
+    }
     return hipGetLastError();
 }
 

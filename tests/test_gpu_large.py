@@ -1,6 +1,10 @@
-"""GPU parity at the full Toeplitz size (n = 2^30, m = 2^29, transform length 2^31
-over the 64-bit field): sampled output words against the oracle, computed one
-row at a time, plus GF(2) bilinearity of the whole output."""
+"""GPU parity at the full Toeplitz size (n = 2^30, m = 2^29): the library's default
+plan (two pieces, transforms of 2^30 over 3*2^30+1) against the oracle on
+sampled output words computed one row at a time, GF(2) bilinearity of the whole
+output, and the whole output of the one-transform plan (length 2^31 over the
+64-bit field) — the same integers, so the same bits."""
+import os
+
 import numpy as np
 import pytest
 
@@ -52,3 +56,21 @@ def test_large_bilinear(large):
     z3 = ctx.extract("toeplitz", torch.bitwise_xor(x, x2), y, job.n, job.m, sync=True)
     assert torch.equal(torch.bitwise_xor(z, z2), z3)
     del x2, z2, z3
+
+
+def test_large_two_piece_equals_64bit_transform(large):
+    import torch
+
+    import paper_2402_09481_amd as P
+    ctx, job, x, y, z = large
+    os.environ["EXT_FORCE_FIELD"] = "gl"
+    try:
+        cgl = P.Context(0)
+    finally:
+        del os.environ["EXT_FORCE_FIELD"]
+    show_case("toeplitz_large: 64-bit single transform")
+    z64 = cgl.extract("toeplitz", x, y, job.n, job.m, sync=True)
+    assert torch.equal(z, z64)
+    del z64
+    cgl.close()
+    torch.cuda.empty_cache()

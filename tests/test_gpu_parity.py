@@ -46,6 +46,21 @@ def ctx_p0():
     c.close()
 
 
+@pytest.fixture(scope="module")
+def ctx_2p():
+    """A context that runs every Toeplitz shape with n >= 128 as the two-piece
+    schedule (input split in two word-aligned halves, products added in the
+    transform domain of 3*2^30+1), at small sizes."""
+    import paper_2402_09481_amd as P
+    os.environ["EXT_FORCE_FIELD"] = "p0x2"
+    try:
+        c = P.Context(0)
+    finally:
+        del os.environ["EXT_FORCE_FIELD"]
+    yield c
+    c.close()
+
+
 def seed_len(kind, n, m):
     return {"toeplitz": n + m - 1, "circulant": n + 1, "dodis": n}[kind]
 
@@ -130,6 +145,13 @@ def test_p0_field_path(ctx_p0, kind, n, m):
     run_case(ctx_p0, kind, n, m, "paper", seed=5 * n + m)
     if kind == "toeplitz":
         run_case(ctx_p0, kind, n, m, "linear", seed=7 * n + m)
+
+
+@pytest.mark.parametrize("n,m", [(128, 1), (129, 64), (200, 199), (1000, 1), (4097, 2048), (9000, 7000),
+                                 (65539, 65539), (100000, 50000), (1 << 20, 1 << 19), ((1 << 21) + 77, 300)])
+def test_two_piece_schedule(ctx_2p, n, m):
+    run_case(ctx_2p, "toeplitz", n, m, "paper", seed=11 * n + m)
+    run_case(ctx_2p, "toeplitz", n, m, "linear", seed=13 * n + m, px=0.3)
 
 
 def test_dodis_degenerate_inputs(ctx):
