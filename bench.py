@@ -117,6 +117,27 @@ def profiled_vn_traffic(n: int):
     return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
+def cpu_ntt_baseline(lg: int = 22):
+    """The single-threaded CPU NTT (`baseline/`, the 64-bit prime of the headline
+    configuration) timed on a Toeplitz extraction whose transform is 2^lg (n = 2^(lg-1),
+    m = 2^(lg-2)), and its time scaled to the headline's 2^31 transform by L log L."""
+    import baseline
+    import workloads as W
+    n, m = 1 << (lg - 1), 1 << (lg - 2)
+    g = W.rng(W.BASE_SEED + 12)
+    x, y = W.bernoulli_bits(g, n, 0.4), W.bernoulli_bits(g, n + m - 1, 0.5)
+    baseline.toeplitz(x[:1], y[:1], 1, 1)  # build and load outside the timing
+    t0 = time.perf_counter()
+    baseline.toeplitz(x, y, n, m)
+    dt = time.perf_counter() - t0
+    L, LH = 1 << lg, 1 << 31
+    t_head = dt * (LH * 31) / (L * lg)
+    return {"value": round(m / dt / 1e6, 3), "unit": "Mbit/s", "cores": 1, "kind": "cpu_ntt",
+            "sample": "Toeplitz n=2^%d, m=2^%d, transform 2^%d over 2^64-2^32+1, %.2f s" % (lg - 1, lg - 2, lg, dt),
+            "headline_extrapolated": {"value": round((1 << 29) / t_head / 1e6, 3), "unit": "Mbit/s",
+                                      "seconds": round(t_head, 1), "scaling": "L log2 L to L = 2^31"}}
+
+
 def cpu_baseline(job, seconds: float):
     """Oracle rows of the same workload for about `seconds` of one core."""
     import oracle
@@ -459,6 +480,8 @@ def main():
     if args.cpu_seconds > 0:
         log("cpu baseline (oracle, %.0f s budget)" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(job, args.cpu_seconds)
+        log("cpu NTT baseline (one thread)")
+        out["cpu_ntt"] = cpu_ntt_baseline()
     if args.batched:
         out["batched"] = run_batched(log)
     if args.paper_shapes:
