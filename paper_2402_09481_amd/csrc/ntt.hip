@@ -259,6 +259,17 @@ struct Ends {
 
 // ------------------------------------------------------------------ strided pass
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2 and address
+// translation cache) round-robin by index. Tile = this remap of the index gives
+// every XCD one contiguous run of tiles, so neighbouring column groups (the same
+// rows, the same memory pages) are read through the same L2. A bijection when
+// the grid is a multiple of 8, the identity otherwise.
+__device__ inline uint64_t xcd_tile(uint64_t b, uint64_t nb) {
+    constexpr uint64_t XCDS = 8;
+    if (nb % XCDS) return b;
+    return (b % XCDS) * (nb / XCDS) + b / XCDS;
+}
+
 struct KArgs {
     const JobDev *jobs;
     JobDev one;
@@ -279,7 +290,9 @@ __global__ void __launch_bounds__((Tile<F, LGR, true>::NT)) k_strided(KArgs a) {
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
     T *data = (T *)(a.which ? J.B : J.A);
     const uint64_t colTiles = a.S / C;
-    const uint64_t tile = blockIdx.x;
+    // (measured: the remap helps the value passes and slows the bit-reading first
+    // forward pass)
+    const uint64_t tile = (MODE == S_FWD || MODE == S_INV) ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
     const uint64_t blk = tile / colTiles, ct = tile - blk * colTiles;
     const uint64_t base = blk * a.Mprev + ct * C;
     const int shift = F::LGMAX - (63 - __builtin_clzll(a.Mprev));  // 2^LGMAX / Mprev = 2^shift
@@ -293,6 +306,14 @@ __global__ void __launch_bounds__((Tile<F, LGR, true>::NT)) k_strided(KArgs a) {
         for (int q = 0; q < GPT; ++q) {
             int c, j;
             Tl::template coords<RAD>(q, c, j);
+            // inverse: twiddle w^-(col r) for rows r = j + t R/RAD, a geometric
+            // sequence in t: two table twiddles per group, then products
+            T wt = T(), st = T();
+            if constexpr (INV) {
+                const uint64_t col = ct * C + c;
+                wt = twiddle<F>(a.tb, (uint64_t(0) - ((col * (uint64_t)j) << shift)) & emask);
+                st = twiddle<F>(a.tb, (uint64_t(0) - ((col * (uint64_t)(R / RAD)) << shift)) & emask);
+            }
 #pragma unroll
             for (int t = 0; t < RAD; ++t) {
                 const int r = j + t * (R / RAD);
@@ -304,8 +325,8 @@ __global__ void __launch_bounds__((Tile<F, LGR, true>::NT)) k_strided(KArgs a) {
                     x = data[gi];
                 }
                 if constexpr (INV) {
-                    uint64_t E = ((ct * C + c) * (uint64_t)r) << shift;
-                    x = F::mul_tw(x, twiddle<F>(a.tb, (uint64_t(0) - E) & emask));
+                    x = F::mul_tw(x, wt);
+                    if (t + 1 < RAD) wt = F::tw_combine(wt, st);
                 }
                 v[q * RAD + t] = x;
             }
@@ -319,14 +340,21 @@ __global__ void __launch_bounds__((Tile<F, LGR, true>::NT)) k_strided(KArgs a) {
         for (int q = 0; q < GPT; ++q) {
             int c, j;
             Tl::template coords<RAD>(q, c, j);
+            // forward: twiddle w^(col r), the same geometric sequence in t
+            T wt = T(), st = T();
+            if constexpr (MODE == S_FWD || MODE == S_FWD_BITS) {
+                const uint64_t col = ct * C + c;
+                wt = twiddle<F>(a.tb, ((col * (uint64_t)j) << shift) & emask);
+                st = twiddle<F>(a.tb, ((col * (uint64_t)(R / RAD)) << shift) & emask);
+            }
 #pragma unroll
             for (int t = 0; t < RAD; ++t) {
                 const int r = j + t * (R / RAD);
                 const uint64_t gi = base + (uint64_t)r * a.S + c;
                 T x = v[q * RAD + t];
                 if constexpr (MODE == S_FWD || MODE == S_FWD_BITS) {
-                    uint64_t E = ((ct * C + c) * (uint64_t)r) << shift;
-                    data[gi] = F::mul_tw(x, twiddle<F>(a.tb, E));
+                    data[gi] = F::mul_tw(x, wt);
+                    if (t + 1 < RAD) wt = F::tw_combine(wt, st);
                 } else if constexpr (MODE == S_INV) {
                     data[gi] = x;
                 } else {
