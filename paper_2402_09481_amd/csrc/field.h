@@ -163,33 +163,48 @@ struct FGL {
         uint64_t s = a + b;
         return s + (s < b ? EPS : 0ull);
     }
-    // a - b for any a < 2^64 and b < P: after a borrow a - b + 2^64 > EPS, so
-    // removing EPS (the value of the borrowed 2^64) cannot borrow again.
+    // a - b for any a < 2^64 and b < P, on 32-bit halves so that the borrow of
+    // the high half selects the correction: after a borrow a - b + 2^64 > EPS, so
+    // adding P = 2^64 - EPS (low half + 1, high half - 1) cannot wrap again.
     __device__ static inline uint64_t sub(uint64_t a, uint64_t b) {
-        uint64_t d = a - b;
-        return d - (a < b ? EPS : 0ull);
+        unsigned b0, b1, k, k2;
+        const uint32_t d0 = __builtin_subc((uint32_t)a, (uint32_t)b, 0u, &b0);
+        const uint32_t d1 = __builtin_subc((uint32_t)(a >> 32), (uint32_t)(b >> 32), b0, &b1);
+        const uint32_t e0 = __builtin_addc(d0, 0u, b1, &k);
+        const uint32_t e1 = __builtin_addc(d1, b1 ? 0xFFFFFFFFu : 0u, k, &k2);
+        return ((uint64_t)e1 << 32) | e0;
     }
-    // 128-bit x = x3*2^96 + x2*2^64 + lo  ->  lo + x2*(2^32 - 1) - x3  (mod P)
+    // 128-bit x = x3*2^96 + x2*2^64 + lo (any limbs). With 2^64 = EPS and
+    // 2^96 = -1: x3*2^96 + x2*2^64 = x2*EPS - x3 = (x2 - 1)*EPS + ~x3 + [x2 == 0],
+    // where (x2 - 1 mod 2^32)*EPS + ~x3 <= EPS^2 is one multiply-add and the
+    // [x2 == 0] term is the borrow of x2 - 1, fed in as the carry of the next add.
+    // A wrap of lo + v past 2^64 is worth EPS; after it the sum is at most
+    // EPS^2 + EPS, so adding EPS cannot wrap again.
     __device__ static inline uint64_t reduce(uint32_t x3, uint32_t x2, uint64_t lo) {
-        uint64_t r;
-        // lo + x2*EPS < 2^65; a wrap leaves r <= 2^64 - 2^33, so +EPS cannot wrap
-        bool c = __builtin_add_overflow(lo, (uint64_t)x2 * EPS, &r);
-        r += c ? EPS : 0ull;
-        uint64_t d = r - (uint64_t)x3;
-        // after a borrow d = r - x3 + 2^64 > 2^64 - 2^32 > EPS: no second borrow
-        return d - (r < (uint64_t)x3 ? EPS : 0ull);
+        unsigned bz, c0, c1, k, k2;
+        const uint32_t x2m1 = __builtin_subc(x2, 1u, 0u, &bz);
+        const uint64_t v = (uint64_t)x2m1 * EPS + (uint64_t)(uint32_t)~x3;
+        const uint32_t r0 = __builtin_addc((uint32_t)lo, (uint32_t)v, bz, &c0);
+        const uint32_t r1 = __builtin_addc((uint32_t)(lo >> 32), (uint32_t)(v >> 32), c0, &c1);
+        const uint32_t s0 = __builtin_addc(r0, c1 ? 0xFFFFFFFFu : 0u, 0u, &k);
+        const uint32_t s1 = __builtin_addc(r1, 0u, k, &k2);
+        return ((uint64_t)s1 << 32) | s0;
     }
     __device__ static inline uint64_t reduce128(uint64_t hi, uint64_t lo) {
         return reduce((uint32_t)(hi >> 32), (uint32_t)hi, lo);
     }
     // a * b mod P (result < 2^64, not necessarily canonical); schoolbook on 32-bit
-    // halves with 32x32+64 multiply-adds.
+    // halves with 32x32+64 multiply-adds. The two high halves of the middle
+    // products are summed into a 33-bit addend of the top product (no overflow:
+    // (2^32-1)^2 + 2^33 - 2 < 2^64), so the top product is already limbs x3:x2.
     __device__ static inline uint64_t mul(uint64_t a, uint64_t b) {
         const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
         const uint64_t t00 = (uint64_t)a0 * b0;
         const uint64_t t10 = (uint64_t)a1 * b0 + (t00 >> 32);
         const uint64_t t01 = (uint64_t)a0 * b1 + (uint32_t)t10;
-        const uint64_t t11 = (uint64_t)a1 * b1 + (t10 >> 32) + (t01 >> 32);  // <= 2^64 - 1
+        unsigned c;
+        const uint32_t s = __builtin_addc((uint32_t)(t10 >> 32), (uint32_t)(t01 >> 32), 0u, &c);
+        const uint64_t t11 = (uint64_t)a1 * b1 + (((uint64_t)c << 32) | s);
         const uint64_t lo = (t01 << 32) | (uint32_t)t00;
         return reduce((uint32_t)(t11 >> 32), (uint32_t)t11, lo);
     }
@@ -213,10 +228,16 @@ struct FGL {
             return r + (c ? EPS : 0ull);
         } else if constexpr (s < 64) {
             return reduce128(x >> (64 - s), x << s);
+        } else if constexpr (s == 64) {
+            return reduce128(x, 0ull);
         } else {
-            // 64 <= s < 96: (x 2^(s-64)) 2^64 with 2^64 = 2^32 - 1: y 2^32 - y
-            const uint64_t y = canon(mul_pow2<s - 64>(x));
-            return sub(mul_pow2<32>(y), y);
+            // 64 < s < 96, k = s - 64: x 2^k = h 2^64 + y (h < 2^32), so
+            // x 2^s = h 2^128 + y 2^64 with 2^128 = -2^32; -h 2^32 is taken as
+            // P - h 2^32 = (~h) 2^32 + 1, the low word beside limbs y = x3:x2.
+            constexpr int k = s - 64;
+            const uint64_t y = x << k;
+            const uint32_t h = (uint32_t)(x >> (64 - k));
+            return reduce128(y, ((uint64_t)(uint32_t)~h << 32) | 1u);
         }
     }
     // x * w_RAD^K (the compile-time roots of the in-register DFTs)
