@@ -155,6 +155,14 @@ struct Tile {
     // contiguous tiles pad one word per 16 so that power-of-two strides spread over banks
     static constexpr int RP = STRIDED ? R : R + R / 16;
     static constexpr int LDS_WORDS = STRIDED ? C * R : C * RP;
+    // Waves per SIMD that strided kernels promise the register allocator: as
+    // many as the LDS admits (160 KiB per CU, 4 SIMDs), at most 8. A register
+    // count above that would leave LDS idle and halve the resident workgroups
+    // (the bit-reading first pass of 32-bit fields needed 72 registers for 64).
+    static constexpr int LDS_BYTES = LDS_WORDS * (int)sizeof(T);
+    static constexpr int WG_BY_LDS = (160 * 1024) / LDS_BYTES;
+    static constexpr int WPE0 = WG_BY_LDS * (NT / 64) / 4;
+    static constexpr int WAVES_PER_SIMD = WPE0 < 1 ? 1 : (WPE0 > 8 ? 8 : WPE0);
     __device__ static inline int lidx(int c, int r) { return STRIDED ? r * C + c : c * RP + r + (r >> 4); }
     template <int RAD>
     __device__ static inline void coords(int q, int &c, int &j) {
@@ -279,7 +287,8 @@ struct KArgs {
 };
 
 template <class F, int LGR, int MODE>
-__global__ void __launch_bounds__((Tile<F, LGR, true>::NT)) k_strided(KArgs a) {
+__global__ void __launch_bounds__((Tile<F, LGR, true>::NT))
+__attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true>::WAVES_PER_SIMD))) k_strided(KArgs a) {
     using Tl = Tile<F, LGR, true>;
     using T = typename F::T;
     constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
@@ -320,7 +329,11 @@ __global__ void __launch_bounds__((Tile<F, LGR, true>::NT)) k_strided(KArgs a) {
                 const uint64_t gi = base + (uint64_t)r * a.S + c;
                 T x;
                 if constexpr (MODE == S_FWD_BITS) {
-                    x = F::from_bit(getbit(J.eb[a.which], gi));
+                    // a row segment of the tile is C adjacent bits starting at a
+                    // multiple of C: one C-bit unit, the same address for every
+                    // lane of the row
+                    const Unit *ub = (const Unit *)J.eb[a.which];
+                    x = F::from_bit((uint32_t)(ub[(gi - c) / C] >> c) & 1u);
                 } else {
                     x = data[gi];
                 }
