@@ -138,7 +138,7 @@ __device__ inline typename F::T twiddle(const Tables &tb, uint64_t E) {
 
 // ------------------------------------------------------------------ tile geometry
 
-template <class F, int LGR, bool STRIDED>
+template <class F, int LGR, bool STRIDED, bool RF_SECOND = true>
 struct Tile {
     using T = typename F::T;
     static constexpr int R = 1 << LGR;
@@ -175,9 +175,19 @@ struct Tile {
             c = g / (R / RAD);
         }
     }
-    // radix and span of step s
+    // Radix of step s. A step of radix r multiplies (r-1)/r of its values by
+    // twiddles, except the first step, which has none; so with RF_SECOND the
+    // leftover radix RF goes second, after a radix-16 step (9 levels: 16*2*16
+    // takes 1/2 + 15/16 twiddle products per value where 2*16*16 takes
+    // 15/16 + 15/16). Otherwise RF is the forward's first and the inverse's last
+    // radix (the fused pass's order: it needs fewer registers there). With two
+    // steps the forward order is always RF, 16 and the inverse 16, RF, so that a
+    // fused pass hands the forward's last radix-16 layout to the inverse's first
+    // step. Every order gives the same transform in the same (natural) order.
     __host__ __device__ static constexpr int radix(int s, bool inv) {
-        return inv ? (s == NSTEPS - 1 ? RF : 16) : (s == 0 ? RF : 16);
+        if (NSTEPS >= 3 && RF_SECOND) return s == 1 ? RF : 16;
+        if (NSTEPS >= 2) return inv ? (s == NSTEPS - 1 ? RF : 16) : (s == 0 ? RF : 16);
+        return RF;
     }
     __host__ __device__ static constexpr int span(int s, bool inv) {
         int ns = 1;
@@ -237,12 +247,76 @@ __device__ inline void step_store_lds(const typename F::T *v, typename F::T *lds
     }
 }
 
+// Stockham twiddles of one step, tw[q RAD + t] = w_(Ns RAD)^(+-t jm) for t >= 1
+// (the values step_compute looks up), loaded ahead of the step that uses them.
+template <class F, class Tl, int RAD>
+__device__ inline void step_twiddles(typename F::T *tw, int Ns, bool inv, const Tables &tb) {
+    using T = typename F::T;
+    const T *twin = (const T *)tb.in;
+    constexpr int GPT = Tl::EPT / RAD;
+#pragma unroll
+    for (int q = 0; q < GPT; ++q) {
+        int c, j;
+        Tl::template coords<RAD>(q, c, j);
+        (void)c;
+        const int jm = j & (Ns - 1);
+        const int scale = (1 << TWIN_LG) / (Ns * RAD);
+#pragma unroll
+        for (int t = 1; t < RAD; ++t) {
+            int e = t * jm * scale;
+            if (inv) e = ((1 << TWIN_LG) - e) & ((1 << TWIN_LG) - 1);
+            tw[q * RAD + t] = twin[e];
+        }
+    }
+}
+
+template <class F, class Tl, int RAD>
+__device__ inline void step_compute_pre(typename F::T *v, const typename F::T *tw, int Ns, bool inv) {
+    constexpr int GPT = Tl::EPT / RAD;
+#pragma unroll
+    for (int q = 0; q < GPT; ++q) {
+        if (Ns > 1) {
+#pragma unroll
+            for (int t = 1; t < RAD; ++t) v[q * RAD + t] = F::mul_tw(v[q * RAD + t], tw[q * RAD + t]);
+        }
+        dft_reg<F, RAD>(&v[q * RAD], inv);
+    }
+}
+
+// As run_steps_from, with each step's twiddle loads issued one step early (before
+// the LDS exchange that precedes their use), so that their latency overlaps the
+// previous step's arithmetic. Used by the strided tiles of the 64-bit field,
+// which LDS holds to 4 waves per SIMD, so that the prefetch's registers are free.
+template <class F, class Tl, bool INV, int S>
+__device__ inline void run_steps_pre(typename F::T *v, typename F::T *lds, const Tables &tb,
+                                     const typename F::T *tw) {
+    using T = typename F::T;
+    if constexpr (S < Tl::NSTEPS) {
+        constexpr int RAD = Tl::radix(S, INV);
+        constexpr int NS = Tl::span(S, INV);
+        if constexpr (S > 0) step_load_lds<F, Tl, RAD>(v, lds);
+        T twn[Tl::EPT];
+        if constexpr (S + 1 < Tl::NSTEPS)
+            step_twiddles<F, Tl, Tl::radix(S + 1, INV)>(twn, Tl::span(S + 1, INV), INV, tb);
+        step_compute_pre<F, Tl, RAD>(v, tw, NS, INV);
+        if constexpr (S + 1 < Tl::NSTEPS) {
+            __syncthreads();
+            step_store_lds<F, Tl, RAD>(v, lds, NS);
+            __syncthreads();
+            run_steps_pre<F, Tl, INV, S + 1>(v, lds, tb, twn);
+        }
+    }
+}
+
 // Run steps [s0, s1) of a transform whose inputs for step s0 are already in
 // registers; the outputs of step s1-1 stay in registers (positions of the
 // last-step layout if s1 == NSTEPS). LDS exchanges in between.
-template <class F, class Tl, bool INV, int S>
+template <class F, class Tl, bool INV, int S, bool PRE = false>
 __device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, const Tables &tb) {
-    if constexpr (S < Tl::NSTEPS) {
+    if constexpr (S == 0 && PRE) {
+        typename F::T tw0[Tl::EPT];  // the first step has no twiddles
+        run_steps_pre<F, Tl, INV, 0>(v, lds, tb, tw0);
+    } else if constexpr (S < Tl::NSTEPS) {
         constexpr int RAD = Tl::radix(S, INV);
         constexpr int NS = Tl::span(S, INV);
         if constexpr (S > 0) {
@@ -345,7 +419,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true>::WAVES_PER_SIMD))) k_strid
             }
         }
     }
-    run_steps_from<F, Tl, INV, 0>(v, lds, a.tb);
+    run_steps_from<F, Tl, INV, 0, (F::WORD_BITS == 64 && LGR <= 9)>(v, lds, a.tb);
     {
         constexpr int RAD = Ends<Tl, INV>::RAD_LAST;
         constexpr int GPT = EPT / RAD;
@@ -389,7 +463,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true>::WAVES_PER_SIMD))) k_strid
 
 template <class F, int LGR, int MODE>
 __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
-    using Tl = Tile<F, LGR, false>;
+    using Tl = Tile<F, LGR, false, (MODE == C_FWD)>;
     using T = typename F::T;
     constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
     __shared__ T lds[Tl::LDS_WORDS];
