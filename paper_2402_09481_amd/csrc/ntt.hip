@@ -138,7 +138,7 @@ __device__ inline typename F::T twiddle(const Tables &tb, uint64_t E) {
 
 // ------------------------------------------------------------------ tile geometry
 
-template <class F, int LGR, bool STRIDED, bool RF_SECOND = true>
+template <class F, int LGR, bool STRIDED, int ORDER = 1>
 struct Tile {
     using T = typename F::T;
     static constexpr int R = 1 << LGR;
@@ -176,16 +176,17 @@ struct Tile {
         }
     }
     // Radix of step s. A step of radix r multiplies (r-1)/r of its values by
-    // twiddles, except the first step, which has none; so with RF_SECOND the
-    // leftover radix RF goes second, after a radix-16 step (9 levels: 16*2*16
-    // takes 1/2 + 15/16 twiddle products per value where 2*16*16 takes
-    // 15/16 + 15/16). Otherwise RF is the forward's first and the inverse's last
-    // radix (the fused pass's order: it needs fewer registers there). With two
-    // steps the forward order is always RF, 16 and the inverse 16, RF, so that a
-    // fused pass hands the forward's last radix-16 layout to the inverse's first
-    // step. Every order gives the same transform in the same (natural) order.
+    // twiddles, except the first step, which has none; so the leftover radix RF
+    // is best anywhere but first (9 levels: 16*2*16 takes 1/2 + 15/16 twiddle
+    // products per value where 2*16*16 takes 15/16 + 15/16). ORDER 1: RF second
+    // in both directions; ORDER 2: RF second in the forward and last in the
+    // inverse (the fused pass: as cheap, and fewer registers); ORDER 0: RF first
+    // in the forward and last in the inverse. With two steps the forward order
+    // is always RF, 16 and the inverse 16, RF, so that a fused pass hands the
+    // forward's last radix-16 layout to the inverse's first step. Every order
+    // gives the same transform in the same (natural) order.
     __host__ __device__ static constexpr int radix(int s, bool inv) {
-        if (NSTEPS >= 3 && RF_SECOND) return s == 1 ? RF : 16;
+        if (NSTEPS >= 3 && (ORDER == 1 || (ORDER == 2 && !inv))) return s == 1 ? RF : 16;
         if (NSTEPS >= 2) return inv ? (s == NSTEPS - 1 ? RF : 16) : (s == 0 ? RF : 16);
         return RF;
     }
@@ -463,7 +464,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true>::WAVES_PER_SIMD))) k_strid
 
 template <class F, int LGR, int MODE>
 __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
-    using Tl = Tile<F, LGR, false, (MODE == C_FWD)>;
+    using Tl = Tile<F, LGR, false, (MODE == C_FWD ? 1 : 2)>;
     using T = typename F::T;
     constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
     __shared__ T lds[Tl::LDS_WORDS];
