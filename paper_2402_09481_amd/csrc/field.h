@@ -185,7 +185,12 @@ struct FGL {
         const uint32_t x2m1 = __builtin_subc(x2, 1u, 0u, &bz);
         const uint64_t v = (uint64_t)x2m1 * EPS + (uint64_t)(uint32_t)~x3;
         const uint32_t r0 = __builtin_addc((uint32_t)lo, (uint32_t)v, bz, &c0);
-        const uint32_t r1 = __builtin_addc((uint32_t)(lo >> 32), (uint32_t)(v >> 32), c0, &c1);
+        uint32_t r1 = __builtin_addc((uint32_t)(lo >> 32), (uint32_t)(v >> 32), c0, &c1);
+#if defined(__HIP_DEVICE_COMPILE__)
+        // keep r1 in a register: otherwise r1 + k is refolded into a three-input
+        // add that needs c0 as a value (two more instructions); emits no code
+        asm("" : "+v"(r1));
+#endif
         const uint32_t s0 = __builtin_addc(r0, c1 ? 0xFFFFFFFFu : 0u, 0u, &k);
         const uint32_t s1 = __builtin_addc(r1, 0u, k, &k2);
         return ((uint64_t)s1 << 32) | s0;
