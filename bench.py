@@ -43,7 +43,10 @@ def kernel_bytes(label: str, L: int, w: int, n: int, N: int, m: int) -> int:
     """Algorithmic HBM bytes of one launch of a pass kernel (label from the library's tracer).
     strided mode 0 (embed bits): writes L words, reads the packed input (n or N bits);
     strided mode 1/2 and contiguous mode 0: read + write L words; contiguous mode 1
-    (fused seed transform, product, inverse): reads 2L, writes L; strided mode 3
+    (fused seed transform, product, inverse): reads 2L, writes L; two-piece schedule:
+    contiguous mode 3 (second piece's seed level times its input spectrum) reads 2L, writes
+    L, contiguous mode 2 (first piece's fused pass plus that product) reads 3L, writes L;
+    strided mode 3
     (last inverse pass): reads L words, writes m parity bits; pack: m bits in, m bits out;
     embed: both packed inputs in, both L-bit coefficient strings out; ptrans: L parity bits
     in and out."""
@@ -63,8 +66,8 @@ def kernel_bytes(label: str, L: int, w: int, n: int, N: int, m: int) -> int:
         if mode == 3:
             return Lw + m // 8
         return 2 * Lw
-    if kind == "contig":  # mode 2: the two-piece fused pass (4 arrays in, 1 out)
-        return 5 * Lw if mode == 2 else 3 * Lw if mode == 1 else 2 * Lw
+    if kind == "contig":  # mode 2: the two-piece fused pass (3 arrays in, 1 out)
+        return 4 * Lw if mode == 2 else 3 * Lw if mode in (1, 3) else 2 * Lw
     return 0
 
 

@@ -341,7 +341,7 @@ uint64_t pointwise_K(const Plan &p) {
 }
 
 // piece: 0 for a single transform and for the first piece of the two-piece
-// schedule (which also points at the second piece's spectra), 1 for its second.
+// schedule (which also points at the second piece's product), 1 for its second.
 JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint64_t *y, uint64_t *z, int32_t *status,
                    uint32_t flags, char *ws, int piece = 0) {
     JobDev j;
@@ -353,8 +353,7 @@ JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint6
         j.pb = (uint64_t *)(ws + l.pb);
         j.S = j.A;
         if (p.pieces == 2 && piece == 0) {
-            j.S2 = ws + l.a2;
-            j.T2 = ws + l.b2;
+            j.S2 = ws + l.b2;  // the second piece's product spectrum (C_PROD)
         }
         j.eb[0] = (uint64_t *)(ws + l.eb0);
         j.eb[1] = (uint64_t *)(ws + l.eb1);
@@ -636,9 +635,10 @@ std::string pass_label(const char *what, int field, int lgr, int mode, int which
 // COLD: both transforms, product, inverse, parity. SEED_ONLY: the seed's full
 // forward transform into B (a seed-cache entry). WARM: the input's transform
 // fused with the cached seed spectrum S, inverse in A, parity.
-// FWD_BOTH: both operands' full forward transforms (the second piece of the
-// two-piece schedule); TWO: the first piece, whose fused pass adds the second
-// piece's product.
+// FWD_BOTH: the second piece of the two-piece schedule: both operands' forward
+// transforms, the seed's last level multiplied by the input's spectrum (the
+// piece's product, left in B); TWO: the first piece, whose fused pass adds the
+// second piece's product.
 enum Phase { PH_COLD = 0, PH_SEED_ONLY = 1, PH_WARM = 2, PH_FWD_BOTH = 3, PH_TWO = 4 };
 
 hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs_dev, const JobDev *one,
@@ -687,9 +687,11 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         PassLaunch pl;
         pl.field = p.field;
         pl.lgr = lc;
-        pl.mode = (ph == PH_SEED_ONLY || ph == PH_FWD_BOTH || ((ph == PH_COLD || ph == PH_TWO) && which == 0))
-                      ? C_FWD
-                      : ph == PH_TWO ? C_FUSED2 : C_FUSED;
+        pl.mode = (ph == PH_FWD_BOTH && which == 1)
+                      ? C_PROD
+                      : (ph == PH_SEED_ONLY || ph == PH_FWD_BOTH || ((ph == PH_COLD || ph == PH_TWO) && which == 0))
+                            ? C_FWD
+                            : ph == PH_TWO ? C_FUSED2 : C_FUSED;
         pl.which = which;
         pl.S = 0;
         pl.Mprev = 0;

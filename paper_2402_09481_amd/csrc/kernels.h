@@ -41,8 +41,7 @@ struct JobDev {
     void *A;           // L words: the input transform, then its spectrum
     void *B;           // L words: the seed transform, then the product, then the convolution
     void *S;           // spectrum operand of the fused pass: A, or a cached seed spectrum
-    const void *S2;    // two-piece schedule: the second piece's input spectrum ...
-    const void *T2;    // ... and seed spectrum (C_FUSED2 adds their product)
+    const void *S2;    // two-piece schedule: the second piece's product spectrum (C_FUSED2 adds it)
     uint64_t *pb;      // packed parity of coefficients [0, out_len) (+1 spare word)
     uint64_t *eb[2];   // the two embedded coefficient vectors as L-bit strings (multi-pass only)
     uint32_t *flags;   // degenerate check: flags[0] = any one bit, flags[1] = any zero bit
@@ -85,9 +84,11 @@ int max_small_lg();
 enum StridedMode : int { S_FWD_BITS = 0, S_FWD = 1, S_INV = 2, S_INV_PARITY = 3 };
 // Contiguous pass over rows of R = 2^lgr consecutive words (last level).
 // C_FUSED: the seed's last forward level, the product with the input spectrum S
-// (times L^-1) and the first inverse level. C_FUSED2: the same with the second
-// piece's product S2 * T2 added before the inverse (two-piece schedule).
-enum ContigMode : int { C_FWD = 0, C_FUSED = 1, C_FUSED2 = 2 };
+// (times L^-1) and the first inverse level. Two-piece schedule: C_PROD is the
+// second piece's seed last forward level times its input spectrum S, written back
+// (the piece's product spectrum); C_FUSED2 is C_FUSED of the first piece with
+// that product S2 added before the factor L^-1 and the inverse.
+enum ContigMode : int { C_FWD = 0, C_FUSED = 1, C_FUSED2 = 2, C_PROD = 3 };
 
 struct PassLaunch {
     int field, lgr, mode;

@@ -486,14 +486,25 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             for (int t = 0; t < RAD; ++t) v[q * RAD + t] = data[base + (uint64_t)c * R + j + t * (R / RAD)];
         }
     }
-    run_steps_from<F, Tl, false, 0>(v, lds, a.tb);
     constexpr int RADL = Ends<Tl, false>::RAD_LAST;
     constexpr int GPTL = EPT / RADL;
+    // C_PROD: the spectrum operand's values are loaded before the transform, so
+    // that their latency overlaps it (its registers are free under the LDS limit)
+    T sv[MODE == C_PROD ? EPT : 1];
+    if constexpr (MODE == C_PROD) {
+#pragma unroll
+        for (int q = 0; q < GPTL; ++q) {
+            int c, j;
+            Tl::template coords<RADL>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RADL; ++t) sv[q * RADL + t] = spec[base + (uint64_t)c * R + j + t * (R / RADL)];
+        }
+    }
+    run_steps_from<F, Tl, false, 0>(v, lds, a.tb);
     if constexpr (MODE == C_FUSED || MODE == C_FUSED2) {
         static_assert(Ends<Tl, true>::RAD_FIRST == RADL, "register hand-over needs equal radices");
         const T K = (T)J.K;
-        const T *spec2 = (const T *)J.S2;
-        const T *seed2 = (const T *)J.T2;
+        const T *prod2 = (const T *)J.S2;
 #pragma unroll
         for (int q = 0; q < GPTL; ++q) {
             int c, j;
@@ -502,7 +513,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             for (int t = 0; t < RADL; ++t) {
                 const uint64_t gi = base + (uint64_t)c * R + j + t * (R / RADL);
                 T prod = F::mont(v[q * RADL + t], spec[gi]);
-                if constexpr (MODE == C_FUSED2) prod = F::add(prod, F::as_b(F::mont(spec2[gi], seed2[gi])));
+                if constexpr (MODE == C_FUSED2) prod = F::add(prod, F::as_b(prod2[gi]));
                 v[q * RADL + t] = F::mont(prod, K);
             }
         }
@@ -522,7 +533,13 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             int c, j;
             Tl::template coords<RADL>(q, c, j);
 #pragma unroll
-            for (int t = 0; t < RADL; ++t) data[base + (uint64_t)c * R + j + t * (R / RADL)] = v[q * RADL + t];
+            for (int t = 0; t < RADL; ++t) {
+                const uint64_t gi = base + (uint64_t)c * R + j + t * (R / RADL);
+                if constexpr (MODE == C_PROD)
+                    data[gi] = F::mont(v[q * RADL + t], sv[q * RADL + t]);
+                else
+                    data[gi] = v[q * RADL + t];
+            }
         }
     }
 }
@@ -865,12 +882,16 @@ template <class F, int LGR>
 static hipError_t contig_one(const PassLaunch &p, const KArgs &ka, hipStream_t s) {
     using Tl = Tile<F, LGR, false>;
     dim3 grid((unsigned)p.tiles, p.njobs), block(Tl::NT);
-    if (p.mode == C_FUSED2) {
+    if (p.mode == C_FUSED2 || p.mode == C_PROD) {
         // only the 32-bit field 3*2^30+1 runs the two-piece schedule
-        if constexpr (std::is_same<F, FP0>::value)
-            hipLaunchKernelGGL((k_contig<F, LGR, C_FUSED2>), grid, block, 0, s, ka);
-        else
+        if constexpr (std::is_same<F, FP0>::value) {
+            if (p.mode == C_FUSED2)
+                hipLaunchKernelGGL((k_contig<F, LGR, C_FUSED2>), grid, block, 0, s, ka);
+            else
+                hipLaunchKernelGGL((k_contig<F, LGR, C_PROD>), grid, block, 0, s, ka);
+        } else {
             return hipErrorInvalidValue;
+        }
     } else if (p.mode == C_FUSED) {
         hipLaunchKernelGGL((k_contig<F, LGR, C_FUSED>), grid, block, 0, s, ka);
     } else {
