@@ -565,7 +565,10 @@ struct SmallTile {
         c = 0;
         j = lid() + q * NT;
     }
+    // the leftover radix second in the forward transforms and last in the
+    // inverse (the order of the fused contiguous pass, see Tile::radix)
     __host__ __device__ static constexpr int radix(int s, bool inv) {
+        if (NSTEPS >= 3 && !inv) return s == 1 ? RF : 16;
         return inv ? (s == NSTEPS - 1 ? RF : 16) : (s == 0 ? RF : 16);
     }
     __host__ __device__ static constexpr int span(int s, bool inv) {
