@@ -75,30 +75,55 @@ PROFILE_BYTES = os.path.join(ROOT, "profiles", "toeplitz_n2p30_hbm_bytes.md")
 KERNEL_SOURCES = ["paper_2402_09481_amd/csrc/ntt.hip", "paper_2402_09481_amd/csrc/field.h",
                   "paper_2402_09481_amd/csrc/kernels.h"]
 PROFILE_VN = os.path.join(ROOT, "profiles", "von_neumann_kernel_trace_and_bytes.md")
+PROFILE_VALU = os.path.join(ROOT, "profiles", "toeplitz_n2p30_valu_lds.md")
+VALU_PEAK_T = 256 * 64 * 2.4e9 / 1e12  # lane operations per second, 32-bit VALU, 10^12
 VN_SOURCES = ["paper_2402_09481_amd/csrc/vonneumann.hip", "paper_2402_09481_amd/csrc/kernels.h"]
+
+
+def _profile_blob(path: str, sources):
+    """The machine-readable block of a committed rocprofv3 summary, or None if the
+    summary does not exist or was taken on kernel sources other than these."""
+    import hashlib
+    try:
+        text = open(path).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for fn in sources:
+        h.update(open(os.path.join(ROOT, fn), "rb").read())
+    return blob if h.hexdigest() == blob.get("kernel_sources_sha256") else None
+
+
+def _kernel_name(label: str) -> str:
+    kind = label.split("[")[0]
+    f = dict(kv.split("=") for kv in label.split("[")[1].rstrip("]").split(",")[1:])
+    field = "FGL" if "[u64" in label else "FP0" if "[p0" in label else "FBB"
+    return "k_%s<%s, %s, %s>" % (kind, field, f["lgr"], f["mode"])
 
 
 def profiled_traffic(label: str):
     """HBM bytes (read + write, calibrated) of one launch of the kernel behind a trace
     label, from the committed rocprofv3 summary — None if that summary does not exist or
     was taken on different kernel sources."""
-    import hashlib
-    try:
-        text = open(PROFILE_BYTES).read()
-        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-    except (OSError, IndexError, ValueError):
-        return None
-    h = hashlib.sha256()
-    for fn in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, fn), "rb").read())
-    if h.hexdigest() != blob.get("kernel_sources_sha256"):
-        return None
-    kind = label.split("[")[0]
-    f = dict(kv.split("=") for kv in label.split("[")[1].rstrip("]").split(",")[1:])
-    field = "FGL" if "[u64" in label else "FP0" if "[p0" in label else "FBB"
-    name = "k_%s<%s, %s, %s>" % (kind, field, f["lgr"], f["mode"])
-    e = blob.get("per_launch", {}).get(name)
+    blob = _profile_blob(PROFILE_BYTES, KERNEL_SOURCES)
+    e = None if blob is None else blob.get("per_launch", {}).get(_kernel_name(label))
     return None if e is None else e["read_bytes"] + e["write_bytes"]
+
+
+def valu_view(label: str, avg_ms: float):
+    """The ALU view of one launch: the wave instructions rocprofv3 counted for that
+    kernel (SQ_INSTS_VALU, committed summary of the same kernel sources) as lane
+    operations, over the launch's measured duration, against 256 CUs x 64 lanes x
+    2.4 GHz. None without a matching summary."""
+    blob = _profile_blob(PROFILE_VALU, KERNEL_SOURCES)
+    e = None if blob is None else blob.get("per_launch", {}).get(_kernel_name(label))
+    if e is None:
+        return None
+    lane_ops = e["valu_insts"] * 64
+    achieved = lane_ops / (avg_ms * 1e-3) / 1e12
+    return {"lane_ops_per_launch": int(lane_ops), "achieved": round(achieved, 2), "peak": VALU_PEAK_T,
+            "unit": "T lane-op/s", "frac": round(achieved / VALU_PEAK_T, 4)}
 
 
 def profiled_vn_traffic(n: int):
@@ -230,7 +255,8 @@ def run_headline(args):
                    "n": job.n, "m": job.m, "transform_length": L, "word_bytes": w},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["achieved_GBs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4),
-                     "traffic": profiled_traffic(dom["kernel"]), "algo_bytes_per_launch": dom["algo_bytes"]},
+                     "traffic": profiled_traffic(dom["kernel"]), "algo_bytes_per_launch": dom["algo_bytes"],
+                     "valu": valu_view(dom["kernel"], dom["avg_ms"])},
         "path": {"algo_bytes": path_bytes, "achieved_GBs": round(path_bytes / (ms * 1e-3) / 1e9, 1),
                  "frac_of_hbm_roofline": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                  "roofline_Mbit_s": round(job.m / (path_bytes / (HBM_PEAK_GBS * 1e9)) / 1e6, 1)},

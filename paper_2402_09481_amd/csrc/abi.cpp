@@ -150,6 +150,27 @@ std::vector<typename F::T> table_pow(typename F::T base, size_t count) {
     return t;
 }
 
+// The Stockham step blocks (kernels.h, stk_offset) gathered from the powers of
+// w_(2^TWIN_LG): entry (t, jm) of the block (rad, ns, inverse) is w_(ns rad)^(+-t jm)
+// = w_(2^TWIN_LG)^(+-t jm 2^TWIN_LG / (ns rad)).
+template <class F>
+std::vector<typename F::T> stockham_tables() {
+    const auto in = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << (F::LGMAX - TWIN_LG)), size_t(1) << TWIN_LG);
+    std::vector<typename F::T> out(2 * STK_DIR_WORDS);
+    const int mask = (1 << TWIN_LG) - 1;
+    for (int inv = 0; inv < 2; ++inv)
+        for (int rad = 2; rad <= 16; rad *= 2)
+            for (int ns = 1; ns * rad <= (1 << TWIN_LG); ns *= 2) {
+                const int scale = (1 << TWIN_LG) / (ns * rad);
+                for (int t = 1; t < rad; ++t)
+                    for (int jm = 0; jm < ns; ++jm) {
+                        const int e = t * jm * scale;
+                        out[stk_offset(rad, ns, inv != 0) + (uint64_t)(t - 1) * ns + jm] = in[inv ? (-e) & mask : e];
+                    }
+            }
+    return out;
+}
+
 int ceil_log2(uint64_t v) {
     int l = 0;
     while ((uint64_t(1) << l) < v) ++l;
@@ -989,25 +1010,25 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
         using F = FBB;
         auto lo = table_pow<F>(F::WMAX, size_t(1) << 16);
         auto hi = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << 16), size_t(1) << (F::LGMAX - 16));
-        auto in = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << (F::LGMAX - TWIN_LG)), size_t(1) << TWIN_LG);
+        auto stk = stockham_tables<F>();
         ok = ok && upload(FIELD_BB, 0, lo.data(), lo.size() * 4) && upload(FIELD_BB, 1, hi.data(), hi.size() * 4) &&
-             upload(FIELD_BB, 2, in.data(), in.size() * 4);
+             upload(FIELD_BB, 2, stk.data(), stk.size() * 4);
     }
     {
         using F = FGL;
         auto lo = table_pow<F>(F::WMAX, size_t(1) << 16);
         auto hi = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << 16), size_t(1) << (F::LGMAX - 16));
-        auto in = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << (F::LGMAX - TWIN_LG)), size_t(1) << TWIN_LG);
+        auto stk = stockham_tables<F>();
         ok = ok && upload(FIELD_GL, 0, lo.data(), lo.size() * 8) && upload(FIELD_GL, 1, hi.data(), hi.size() * 8) &&
-             upload(FIELD_GL, 2, in.data(), in.size() * 8);
+             upload(FIELD_GL, 2, stk.data(), stk.size() * 8);
     }
     {
         using F = FP0;
         auto lo = table_pow<F>(F::WMAX, size_t(1) << 16);
         auto hi = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << 16), size_t(1) << (F::LGMAX - 16));
-        auto in = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << (F::LGMAX - TWIN_LG)), size_t(1) << TWIN_LG);
+        auto stk = stockham_tables<F>();
         ok = ok && upload(FIELD_P0, 0, lo.data(), lo.size() * 4) && upload(FIELD_P0, 1, hi.data(), hi.size() * 4) &&
-             upload(FIELD_P0, 2, in.data(), in.size() * 4);
+             upload(FIELD_P0, 2, stk.data(), stk.size() * 4);
     }
     if (ok) ok = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {

@@ -57,12 +57,32 @@ struct JobDev {
 };
 
 struct Tables {
-    const void *lo;  // w_max^j, j < 2^16 (twiddle form)
-    const void *hi;  // w_max^(j 2^16), j < 2^(LGMAX-16)
-    const void *in;  // w_{2^14}^j, j < 2^14
+    const void *lo;   // w_max^j, j < 2^16 (twiddle form)
+    const void *hi;   // w_max^(j 2^16), j < 2^(LGMAX-16)
+    const void *stk;  // Stockham step twiddles (twiddle form), blocks at stk_offset()
 };
 
+// In-pass (Stockham) steps span at most 2^TWIN_LG values.
 constexpr int TWIN_LG = 14;
+
+// Stockham step twiddles. A step of radix RAD and span NS multiplies value t
+// (1 <= t < RAD) of group jm (jm < NS) by w_(NS RAD)^(t jm), or its inverse. The
+// block of (RAD, NS, direction) holds these at [(t - 1) NS + jm]: for one t the
+// lanes of a wave (consecutive jm) read consecutive words, where indexing one
+// table of w_(2^TWIN_LG) by t jm 2^TWIN_LG / (NS RAD) spread a wave's load over
+// up to 64 cache lines. Blocks for RAD in {2, 4, 8, 16} and NS = 1, 2, 4, ...
+// with NS RAD <= 2^TWIN_LG; radix RAD's blocks take (RAD - 1)(2^(TWIN_LG+1)/RAD - 1)
+// words; all forward blocks, then all inverse blocks.
+__host__ __device__ constexpr uint64_t stk_rad_words(int rad) {
+    return (uint64_t)(rad - 1) * ((uint64_t(2) << TWIN_LG) / rad - 1);
+}
+__host__ __device__ constexpr uint64_t stk_rad_base(int rad) {
+    return rad <= 2 ? 0 : stk_rad_base(rad / 2) + stk_rad_words(rad / 2);
+}
+constexpr uint64_t STK_DIR_WORDS = stk_rad_base(32);
+__host__ __device__ constexpr uint64_t stk_offset(int rad, int ns, bool inv) {
+    return (inv ? STK_DIR_WORDS : 0) + stk_rad_base(rad) + (uint64_t)(rad - 1) * (uint64_t)(ns - 1);
+}
 
 // Field selector for the launchers.
 enum FieldId : int { FIELD_BB = 0, FIELD_GL = 1, FIELD_P0 = 2 };

@@ -198,27 +198,23 @@ struct Tile {
 };
 
 // Stockham step compute on registers v (EPT values = EPT/RAD groups of RAD).
-template <class F, class Tl, int RAD>
-__device__ inline void step_compute(typename F::T *v, int Ns, bool inv, const Tables &tb) {
+template <class F, class Tl, int RAD, int NS, bool INV>
+__device__ inline void step_compute(typename F::T *v, const Tables &tb) {
     using T = typename F::T;
-    const T *twin = (const T *)tb.in;
+    static_assert(NS * RAD <= (1 << TWIN_LG) && RAD <= 16, "step beyond the Stockham twiddle blocks");
+    const T *tw = (const T *)tb.stk + stk_offset(RAD, NS, INV);
     constexpr int GPT = Tl::EPT / RAD;
 #pragma unroll
     for (int q = 0; q < GPT; ++q) {
         int c, j;
         Tl::template coords<RAD>(q, c, j);
         (void)c;
-        if (Ns > 1) {
-            int jm = j & (Ns - 1);
-            int scale = (1 << TWIN_LG) / (Ns * RAD);
+        if constexpr (NS > 1) {
+            const int jm = j & (NS - 1);
 #pragma unroll
-            for (int t = 1; t < RAD; ++t) {
-                int e = t * jm * scale;
-                if (inv) e = ((1 << TWIN_LG) - e) & ((1 << TWIN_LG) - 1);
-                v[q * RAD + t] = F::mul_tw(v[q * RAD + t], twin[e]);
-            }
+            for (int t = 1; t < RAD; ++t) v[q * RAD + t] = F::mul_tw(v[q * RAD + t], tw[(t - 1) * NS + jm]);
         }
-        dft_reg<F, RAD>(&v[q * RAD], inv);
+        dft_reg<F, RAD>(&v[q * RAD], INV);
     }
 }
 
@@ -248,26 +244,22 @@ __device__ inline void step_store_lds(const typename F::T *v, typename F::T *lds
     }
 }
 
-// Stockham twiddles of one step, tw[q RAD + t] = w_(Ns RAD)^(+-t jm) for t >= 1
-// (the values step_compute looks up), loaded ahead of the step that uses them.
-template <class F, class Tl, int RAD>
-__device__ inline void step_twiddles(typename F::T *tw, int Ns, bool inv, const Tables &tb) {
+// Stockham twiddles of one step, tw[q RAD + t] = w_(NS RAD)^(+-t jm) for t >= 1
+// (the values step_compute reads), loaded ahead of the step that uses them.
+template <class F, class Tl, int RAD, int NS, bool INV>
+__device__ inline void step_twiddles(typename F::T *tw, const Tables &tb) {
     using T = typename F::T;
-    const T *twin = (const T *)tb.in;
+    static_assert(NS * RAD <= (1 << TWIN_LG) && RAD <= 16, "step beyond the Stockham twiddle blocks");
+    const T *src = (const T *)tb.stk + stk_offset(RAD, NS, INV);
     constexpr int GPT = Tl::EPT / RAD;
 #pragma unroll
     for (int q = 0; q < GPT; ++q) {
         int c, j;
         Tl::template coords<RAD>(q, c, j);
         (void)c;
-        const int jm = j & (Ns - 1);
-        const int scale = (1 << TWIN_LG) / (Ns * RAD);
+        const int jm = j & (NS - 1);
 #pragma unroll
-        for (int t = 1; t < RAD; ++t) {
-            int e = t * jm * scale;
-            if (inv) e = ((1 << TWIN_LG) - e) & ((1 << TWIN_LG) - 1);
-            tw[q * RAD + t] = twin[e];
-        }
+        for (int t = 1; t < RAD; ++t) tw[q * RAD + t] = src[(t - 1) * NS + jm];
     }
 }
 
@@ -298,7 +290,7 @@ __device__ inline void run_steps_pre(typename F::T *v, typename F::T *lds, const
         if constexpr (S > 0) step_load_lds<F, Tl, RAD>(v, lds);
         T twn[Tl::EPT];
         if constexpr (S + 1 < Tl::NSTEPS)
-            step_twiddles<F, Tl, Tl::radix(S + 1, INV)>(twn, Tl::span(S + 1, INV), INV, tb);
+            step_twiddles<F, Tl, Tl::radix(S + 1, INV), Tl::span(S + 1, INV), INV>(twn, tb);
         step_compute_pre<F, Tl, RAD>(v, tw, NS, INV);
         if constexpr (S + 1 < Tl::NSTEPS) {
             __syncthreads();
@@ -324,7 +316,7 @@ __device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, cons
             // inputs of this step come from LDS, written by the previous step
             step_load_lds<F, Tl, RAD>(v, lds);
         }
-        step_compute<F, Tl, RAD>(v, NS, INV, tb);
+        step_compute<F, Tl, RAD, NS, INV>(v, tb);
         if constexpr (S + 1 < Tl::NSTEPS) {
             __syncthreads();  // every read of the previous layout is done
             step_store_lds<F, Tl, RAD>(v, lds, NS);
