@@ -105,9 +105,12 @@ struct FP0 {
         const bool c = __builtin_add_overflow(a, b, &s);
         return (c || s >= P) ? s - P : s;
     }
+    // the borrow of a - b selects the correction (written out, so that operands
+    // known to be high halves of products are not compared as 64-bit values)
     __device__ static inline uint32_t sub(uint32_t a, uint32_t b) {
-        const uint32_t d = a - b;
-        return a < b ? d + P : d;
+        uint32_t d;
+        const bool borrow = __builtin_sub_overflow(a, b, &d);
+        return borrow ? d + P : d;
     }
     // Montgomery product a*b*2^-32 mod P for a, b < P (signed variant, as FBB):
     // hi - mulhi(q, P) lies in (-P, P) since hi = (a b) >> 32 < P.
