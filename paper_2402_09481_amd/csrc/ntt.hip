@@ -390,10 +390,12 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true>::WAVES_PER_SIMD))) k_strid
                 wt = twiddle<F>(a.tb, (uint64_t(0) - ((col * (uint64_t)j) << shift)) & emask);
                 st = twiddle<F>(a.tb, (uint64_t(0) - ((col * (uint64_t)(R / RAD)) << shift)) & emask);
             }
+            // element index of row r = j + t R/RAD, column c: a running sum (one
+            // 64-bit add per element instead of a 32x64-bit product)
+            const uint64_t rstep = (uint64_t)(R / RAD) * a.S;
+            uint64_t gi = base + (uint64_t)j * a.S + c;
 #pragma unroll
-            for (int t = 0; t < RAD; ++t) {
-                const int r = j + t * (R / RAD);
-                const uint64_t gi = base + (uint64_t)r * a.S + c;
+            for (int t = 0; t < RAD; ++t, gi += rstep) {
                 T x;
                 if constexpr (MODE == S_FWD_BITS) {
                     // a row segment of the tile is C adjacent bits starting at a
@@ -427,10 +429,11 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true>::WAVES_PER_SIMD))) k_strid
                 wt = twiddle<F>(a.tb, ((col * (uint64_t)j) << shift) & emask);
                 st = twiddle<F>(a.tb, ((col * (uint64_t)(R / RAD)) << shift) & emask);
             }
+            const uint64_t rstep = (uint64_t)(R / RAD) * a.S;
+            uint64_t gi = base + (uint64_t)j * a.S + c;
 #pragma unroll
-            for (int t = 0; t < RAD; ++t) {
+            for (int t = 0; t < RAD; ++t, gi += rstep) {
                 const int r = j + t * (R / RAD);
-                const uint64_t gi = base + (uint64_t)r * a.S + c;
                 T x = v[q * RAD + t];
                 if constexpr (MODE == S_FWD || MODE == S_FWD_BITS) {
                     data[gi] = F::mul_tw(x, wt);
