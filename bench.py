@@ -265,6 +265,9 @@ def run_headline(args):
         "kernels": kernels,
         "paper_context": "paper: ~1 Mbit/s below n=2^29 and 3-4x lower above (64-bit-class prime), Apple M2 Max CPU",
     }
+    # both fractions, and the one that binds (the higher)
+    rv = out["roofline"]["valu"]
+    out["roofline"]["binding"] = "valu" if rv is not None and rv["frac"] > out["roofline"]["frac"] else "hbm"
     if args.warm:
         # NEXT row f1: the same extraction with the seed's transform cached (a hit
         # skips one of the three transforms; 7 L w algorithmic bytes)
