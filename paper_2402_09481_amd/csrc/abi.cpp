@@ -685,11 +685,11 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         if (ph == PH_WARM && which == 1) continue;
         uint64_t Mprev = L;
         for (int i = 0; i + 1 < p.nlev; ++i) {
-            const Geometry g = strided_geometry(p.field, p.lgr[i]);
             PassLaunch pl;
             pl.field = p.field;
             pl.lgr = p.lgr[i];
             pl.mode = i == 0 ? S_FWD_BITS : S_FWD;
+            const Geometry g = strided_geometry(p.field, p.lgr[i], pl.mode);
             pl.which = which;
             pl.Mprev = Mprev;
             pl.S = Mprev >> p.lgr[i];
@@ -735,11 +735,11 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         M >>= p.lgr[i];
     }
     for (int i = p.nlev - 2; i >= 0; --i) {
-        const Geometry g = strided_geometry(p.field, p.lgr[i]);
         PassLaunch pl;
         pl.field = p.field;
         pl.lgr = p.lgr[i];
         pl.mode = i == 0 ? S_INV_PARITY : S_INV;
+        const Geometry g = strided_geometry(p.field, p.lgr[i], pl.mode);
         pl.which = fused;
         pl.Mprev = mp[i];
         pl.S = mp[i] >> p.lgr[i];

@@ -93,7 +93,7 @@ struct Geometry {
     int C;   // columns (strided) or rows (contiguous) per workgroup
     int NT;  // threads per workgroup
 };
-Geometry strided_geometry(int field, int lgr);
+Geometry strided_geometry(int field, int lgr, int mode);
 Geometry contig_geometry(int field, int lgr);
 int max_strided_lg(int field);
 int max_contig_lg(int field);
@@ -102,6 +102,13 @@ int max_small_lg();
 // Strided pass over columns: the array viewed as (L / Mprev) blocks of R x S
 // (row-major, R = 2^lgr rows at stride S), each column transformed.
 enum StridedMode : int { S_FWD_BITS = 0, S_FWD = 1, S_INV = 2, S_INV_PARITY = 3 };
+// Columns of a strided tile: C adjacent columns make each row segment 128 bytes
+// (32 for 32-bit words, 16 for 64-bit words). (Measured: 8 columns of 64-bit
+// words, 64-byte segments and four 32 KiB workgroups per CU, made the value
+// passes faster and the passes beside them slower by as much.)
+constexpr int strided_cols(int word_bits, int mode) {
+    return (void)mode, word_bits == 32 ? 32 : 16;
+}
 // Contiguous pass over rows of R = 2^lgr consecutive words (last level).
 // C_FUSED: the seed's last forward level, the product with the input spectrum S
 // (times L^-1) and the first inverse level. Two-piece schedule: C_PROD is the

@@ -54,6 +54,10 @@ namespace ext {
 
 __host__ __device__ inline uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
+// An unsigned integer of C bits (one row segment of a strided tile as bits).
+template <int C>
+using UnitOf = typename std::conditional<C == 8, uint8_t, typename std::conditional<C == 16, uint16_t, uint32_t>::type>::type;
+
 __host__ __device__ inline uint32_t getbit(const uint64_t *b, uint64_t i) {
     return (uint32_t)(b[i >> 6] >> (i & 63)) & 1u;
 }
@@ -138,12 +142,12 @@ __device__ inline typename F::T twiddle(const Tables &tb, uint64_t E) {
 
 // ------------------------------------------------------------------ tile geometry
 
-template <class F, int LGR, bool STRIDED, int ORDER = 1>
+template <class F, int LGR, bool STRIDED, int ORDER = 1, int SMODE = S_FWD_BITS>
 struct Tile {
     using T = typename F::T;
     static constexpr int R = 1 << LGR;
     // strided tiles: C adjacent columns give 128-byte row segments in HBM
-    static constexpr int C = STRIDED ? (F::WORD_BITS == 32 ? 32 : 16) : (R >= 2048 ? 1 : 2048 / R);
+    static constexpr int C = STRIDED ? strided_cols(F::WORD_BITS, SMODE) : (R >= 2048 ? 1 : 2048 / R);
     static constexpr int NT0 = C * R / 16;
     static constexpr int NT = NT0 > 1024 ? 1024 : NT0;
     static constexpr int EPT = C * R / NT;
@@ -354,13 +358,13 @@ struct KArgs {
 };
 
 template <class F, int LGR, int MODE>
-__global__ void __launch_bounds__((Tile<F, LGR, true>::NT))
-__attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true>::WAVES_PER_SIMD))) k_strided(KArgs a) {
-    using Tl = Tile<F, LGR, true>;
+__global__ void __launch_bounds__((Tile<F, LGR, true, 1, MODE>::NT))
+__attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))) k_strided(KArgs a) {
+    using Tl = Tile<F, LGR, true, 1, MODE>;
     using T = typename F::T;
     constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
     constexpr bool INV = (MODE == S_INV || MODE == S_INV_PARITY);
-    using Unit = typename std::conditional<C == 16, uint16_t, uint32_t>::type;
+    using Unit = UnitOf<C>;
     __shared__ T lds[C * R];
 
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
@@ -800,7 +804,7 @@ __global__ void __launch_bounds__(256) k_pack(const JobDev *jobs, JobDev one) {
 // through LDS, coalesced on both sides.
 template <int C>
 __global__ void __launch_bounds__(256) k_ptrans(const JobDev *jobs, JobDev one, uint64_t R, uint64_t S) {
-    using Unit = typename std::conditional<C == 16, uint16_t, uint32_t>::type;
+    using Unit = UnitOf<C>;
     constexpr int UPW = 64 / C;  // units per word
     __shared__ Unit tl[64][65];
     const JobDev &J = jobs ? jobs[blockIdx.z] : one;
@@ -865,14 +869,15 @@ static KArgs make_args(const PassLaunch &p, const Tables &t) {
 
 template <class F, int LGR>
 static hipError_t strided_one(const PassLaunch &p, const KArgs &ka, hipStream_t s) {
-    using Tl = Tile<F, LGR, true>;
-    dim3 grid((unsigned)p.tiles, p.njobs), block(Tl::NT);
+    dim3 grid((unsigned)p.tiles, p.njobs);
+#define L1(M) hipLaunchKernelGGL((k_strided<F, LGR, M>), grid, dim3(Tile<F, LGR, true, 1, M>::NT), 0, s, ka)
     switch (p.mode) {
-        case S_FWD_BITS: hipLaunchKernelGGL((k_strided<F, LGR, S_FWD_BITS>), grid, block, 0, s, ka); break;
-        case S_FWD: hipLaunchKernelGGL((k_strided<F, LGR, S_FWD>), grid, block, 0, s, ka); break;
-        case S_INV: hipLaunchKernelGGL((k_strided<F, LGR, S_INV>), grid, block, 0, s, ka); break;
-        default: hipLaunchKernelGGL((k_strided<F, LGR, S_INV_PARITY>), grid, block, 0, s, ka); break;
+        case S_FWD_BITS: L1(S_FWD_BITS); break;
+        case S_FWD: L1(S_FWD); break;
+        case S_INV: L1(S_INV); break;
+        default: L1(S_INV_PARITY); break;
     }
+#undef L1
     return hipGetLastError();
 }
 
@@ -1003,12 +1008,22 @@ int max_strided_lg(int field) { return field == FIELD_GL ? GL_STRIDED_MAX : BB_S
 int max_contig_lg(int field) { return field == FIELD_GL ? GL_CONTIG_MAX : BB_CONTIG_MAX; }
 int max_small_lg() { return SMALL_MAX; }
 
-template <class F>
-static Geometry geo_s(int lgr) {
+template <class F, int M>
+static Geometry geo_s_mode(int lgr) {
     switch (lgr) {
-#define G(L) case L: return Geometry{Tile<F, L, true>::C, Tile<F, L, true>::NT};
+#define G(L) case L: return Geometry{Tile<F, L, true, 1, M>::C, Tile<F, L, true, 1, M>::NT};
         G(7) G(8) G(9) G(10)
 #undef G
+    }
+    return Geometry{0, 0};
+}
+template <class F>
+static Geometry geo_s(int lgr, int mode) {
+    switch (mode) {
+        case S_FWD_BITS: return geo_s_mode<F, S_FWD_BITS>(lgr);
+        case S_FWD: return geo_s_mode<F, S_FWD>(lgr);
+        case S_INV: return geo_s_mode<F, S_INV>(lgr);
+        case S_INV_PARITY: return geo_s_mode<F, S_INV_PARITY>(lgr);
     }
     return Geometry{0, 0};
 }
@@ -1021,8 +1036,8 @@ static Geometry geo_c(int lgr) {
     }
     return Geometry{0, 0};
 }
-Geometry strided_geometry(int field, int lgr) {
-    return field == FIELD_GL ? geo_s<FGL>(lgr) : field == FIELD_P0 ? geo_s<FP0>(lgr) : geo_s<FBB>(lgr);
+Geometry strided_geometry(int field, int lgr, int mode) {
+    return field == FIELD_GL ? geo_s<FGL>(lgr, mode) : field == FIELD_P0 ? geo_s<FP0>(lgr, mode) : geo_s<FBB>(lgr, mode);
 }
 Geometry contig_geometry(int field, int lgr) {
     return field == FIELD_GL ? geo_c<FGL>(lgr) : field == FIELD_P0 ? geo_c<FP0>(lgr) : geo_c<FBB>(lgr);
@@ -1102,9 +1117,11 @@ hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint32_t njobs, cons
     JobDev o;
     if (one) o = *one;
     else std::memset(&o, 0, sizeof(o));
-    const int C = field == FIELD_GL ? 16 : 32;  // strided tile columns: 128-byte rows
+    const int C = strided_cols(field == FIELD_GL ? 64 : 32, S_INV_PARITY);  // columns of the parity pass
     dim3 grid((unsigned)((R + 63) / 64), (unsigned)((S / C + 63) / 64), njobs);
-    if (C == 16)
+    if (C == 8)
+        hipLaunchKernelGGL(k_ptrans<8>, grid, dim3(256), 0, s, jobs, o, R, S);
+    else if (C == 16)
         hipLaunchKernelGGL(k_ptrans<16>, grid, dim3(256), 0, s, jobs, o, R, S);
     else
         hipLaunchKernelGGL(k_ptrans<32>, grid, dim3(256), 0, s, jobs, o, R, S);
