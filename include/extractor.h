@@ -76,14 +76,15 @@ extern "C" {
  * and the two-piece schedule (see EXT_SINGLE_TRANSFORM) ignore the flag. */
 #define EXT_SEED_CACHED 8u
 /* Single calls: compute the extraction as one transform even where the
- * two-piece schedule applies. By default a Toeplitz extraction whose single
- * transform would need the 64-bit field (n + m - 1 > 2^30) while halves of the
- * input fit transforms of at most 2^30 runs as two pieces over 3*2^30+1: the
- * input split at a = ceil(n/2) rounded up to whole words, each half extracted
- * with its own seed window (the sum defining z_i split at j = a), the two
- * products added in the transform domain before one inverse — same bits,
- * 32-bit arithmetic. This flag keeps the one transform of nextpow2(n+m-1) over
- * 2^64 - 2^32 + 1. */
+ * two-piece schedule applies. By default an extraction whose single transform
+ * would need the 64-bit field (n + m - 1 > 2^30; for Dodis and Circulant n is
+ * the circulant length) while halves of the input fit transforms of at most
+ * 2^30 runs as two pieces over 3*2^30+1: the sum over input positions that
+ * defines z_i (Toeplitz directly, Dodis and Circulant in their Toeplitz form
+ * over the reversed input) split at a = ceil(n/2) rounded up to whole words,
+ * each part extracted with its own seed window, the two products added in the
+ * transform domain before one inverse — same bits, 32-bit arithmetic. This flag
+ * keeps the one transform of nextpow2(n+m-1) over 2^64 - 2^32 + 1. */
 #define EXT_SINGLE_TRANSFORM 16u
 
 typedef struct ext_ctx ext_ctx;
@@ -112,7 +113,8 @@ int extract_toeplitz(ext_ctx *ctx, const uint64_t *x, uint64_t n, const uint64_t
  * implementation").
  *   x: n_in bits; n = n_in + 1 must be a prime with primitive root 2
  *   (EXT_ENOTNA otherwise); y: n bits; z: m bits, 1 <= m <= n - 1.
- *   z_i = XOR_{j<n} x'_{(j-i) mod n} y_j. */
+ *   z_i = XOR_{j<n} x'_{(j-i) mod n} y_j.
+ *   flags: optionally EXT_SYNC, EXT_SEED_CACHED, EXT_SINGLE_TRANSFORM. */
 int extract_circulant(ext_ctx *ctx, const uint64_t *x, uint64_t n_in, const uint64_t *y, uint64_t m,
                       uint64_t *z, uint32_t flags, int32_t *status, void *stream);
 
@@ -121,7 +123,8 @@ int extract_circulant(ext_ctx *ctx, const uint64_t *x, uint64_t n_in, const uint
  * indices mod n, Alg. 1).
  *   x, y: n bits each; n prime with primitive root 2 (EXT_ENOTNA otherwise);
  *   1 <= m <= n; x must be neither all zeros nor all ones (device check,
- *   EXT_EDEGENERATE via status). z_i = XOR_{j<n} x_{(j-i) mod n} y_j. */
+ *   EXT_EDEGENERATE via status). z_i = XOR_{j<n} x_{(j-i) mod n} y_j.
+ *   flags: optionally EXT_SYNC, EXT_SEED_CACHED, EXT_SINGLE_TRANSFORM. */
 int extract_dodis(ext_ctx *ctx, const uint64_t *x, const uint64_t *y, uint64_t n, uint64_t m, uint64_t *z,
                   uint32_t flags, int32_t *status, void *stream);
 

@@ -403,12 +403,23 @@ JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint6
         const uint64_t rot = (flags & EXT_SEED_LINEAR) ? 0 : (s.m % N);
         j.ey = Emb{y, N, s.n - 1, N, rot, N, EMB_SEED, 0};
         j.degen_n = 0;
+    } else if (p.pieces == 2) {
+        // Dodis/Circulant as the linear-order Toeplitz extractor of rev(x') with the
+        // periodic seed s_k = y_(k mod n), split at j = a like the Toeplitz shapes:
+        // piece 0 takes rev(x')_0..a-1 = x'_(n-1)..x'_(n-a) with the seed window
+        // s_(n-a).., piece 1 rev(x')_a..n-1 = x'_(n-a-1)..x'_0 with the window s_0..
+        const uint64_t n = s.kind == EXT_KIND_CIRCULANT ? s.n + 1 : s.n;
+        const uint64_t a = p.split;
+        const uint64_t ap = piece ? n - a : a, off = piece ? 0 : n - a, Np = ap + s.m - 1;
+        j.ex = piece ? Emb{x, s.n, n - a, n - a, 0, 0, EMB_REV, 0} : Emb{x, s.n, a, n, 0, 0, EMB_REV, 0};
+        j.ey = Emb{y, n, ap - 1, Np, off % n, n, EMB_SEED, 0};
+        j.degen_n = (s.kind == EXT_KIND_DODIS && piece == 0) ? s.n : 0;
     } else {
         // circulant length n (Circulant: n_in + 1 with x' = [x, 0]); x reversed, the
         // seed repeated with period n, output z_i = XOR_j s_{i-j+n-1} rev(x')_j
         const uint64_t n = s.kind == EXT_KIND_CIRCULANT ? s.n + 1 : s.n;
         const uint64_t N = n + s.m - 1;
-        j.ex = Emb{x, s.n, 0, n, 0, 0, EMB_REV, 0};
+        j.ex = Emb{x, s.n, n, n, 0, 0, EMB_REV, 0};
         j.ey = Emb{y, n, n - 1, N, 0, n, EMB_SEED, 0};
         j.degen_n = s.kind == EXT_KIND_DODIS ? s.n : 0;
     }
@@ -503,37 +514,43 @@ int plan_for(ext_ctx *c, uint64_t Lmin, Plan &p) {
     return EXT_OK;
 }
 
-// Two-piece schedule for Toeplitz shapes beyond one transform of 3*2^30+1: the
-// input is split at a = ceil(n/2) rounded up to whole words, and each half is a
-// Toeplitz extraction with its own seed window of a_p + m - 1 bits, so both run
-// as transforms of length nextpow2(a + m - 1) over 3*2^30+1 (every coefficient
-// of the two convolutions together is at most n < 3*2^30+1). Their products are
-// added in the transform domain before one inverse.
+// Two-piece schedule for shapes beyond one transform of 3*2^30+1. The extraction
+// is a sum over input positions j (Toeplitz: z_i = sum_j s_(i-j+n-1) x_j; Dodis and
+// Circulant: the same with rev(x') and the periodic seed, n the circulant length);
+// it is split at a = ceil(n/2) rounded up to whole words, and each part is a
+// Toeplitz extraction of its a_p input positions with its own seed window of
+// a_p + m - 1 bits, so both run as transforms of length nextpow2(a + m - 1) over
+// 3*2^30+1 (every coefficient of the two convolutions together is at most
+// n < 3*2^30+1). Their products are added in the transform domain before one
+// inverse.
 constexpr uint64_t TWO_PIECE_MIN_N = 128;
 uint64_t two_piece_split(uint64_t n) { return ((n + 1) / 2 + 63) & ~uint64_t(63); }
+// the length of the sum over j: Toeplitz and Dodis n, Circulant n_in + 1
+uint64_t conv_n(const Shape &s) { return s.kind == EXT_KIND_CIRCULANT ? s.n + 1 : s.n; }
 
 // The plan for a shape: a single transform (plan_for), or the two-piece
-// schedule for a Toeplitz shape whose single transform would need the 64-bit
-// field while each piece fits 3*2^30+1 (unless the caller asks for one
-// transform). Forced-field contexts keep single transforms, except force 4
-// (testing aid: two pieces whenever n allows).
+// schedule for a shape whose single transform would need the 64-bit field while
+// each piece fits 3*2^30+1 (unless the caller asks for one transform).
+// Forced-field contexts keep single transforms, except force 4 (testing aid: two
+// pieces whenever n allows).
 int plan_shape(ext_ctx *c, const Shape &s, Plan &p, uint32_t flags = 0) {
     const int force = c ? c->force_field : 0;
-    const bool can_split = s.kind == EXT_KIND_TOEPLITZ && !(flags & EXT_SINGLE_TRANSFORM) && s.n >= TWO_PIECE_MIN_N &&
-                           two_piece_split(s.n) + s.m - 1 <= (uint64_t(1) << FP0::LGMAX);
+    const uint64_t n = conv_n(s);
+    const bool can_split = !(flags & EXT_SINGLE_TRANSFORM) && n >= TWO_PIECE_MIN_N &&
+                           two_piece_split(n) + s.m - 1 <= (uint64_t(1) << FP0::LGMAX);
     if (force == 4) {
         if (!can_split) return make_plan(s.Lmin, 3, p);
-        const int rc = make_plan(two_piece_split(s.n) + s.m - 1, 3, p);
+        const int rc = make_plan(two_piece_split(n) + s.m - 1, 3, p);
         p.pieces = 2;
-        p.split = two_piece_split(s.n);
+        p.split = two_piece_split(n);
         return rc;
     }
     const int rc = plan_for(c, s.Lmin, p);
     if (rc != EXT_OK || force || p.field != FIELD_GL || !can_split) return rc;
     Plan q;
-    if (plan_for(c, two_piece_split(s.n) + s.m - 1, q) != EXT_OK || q.field != FIELD_P0) return rc;
+    if (plan_for(c, two_piece_split(n) + s.m - 1, q) != EXT_OK || q.field != FIELD_P0) return rc;
     q.pieces = 2;
-    q.split = two_piece_split(s.n);
+    q.split = two_piece_split(n);
     p = q;
     return EXT_OK;
 }
@@ -890,7 +907,7 @@ int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint6
         } else if (p.pieces == 2) {
             const JobDev jd1 = make_jobdev(sh, p, x, y, z, st, flags, lease.ptr, 1);
             e = enqueue(c, p, 1, nullptr, &jd1, sh.m, false, s, false, PH_FWD_BOTH);
-            if (e == hipSuccess) e = enqueue(c, p, 1, nullptr, &jd, sh.m, false, s, false, PH_TWO);
+            if (e == hipSuccess) e = enqueue(c, p, 1, nullptr, &jd, sh.m, jd.degen_n != 0, s, false, PH_TWO);
         } else {
             e = enqueue(c, p, 1, nullptr, &jd, sh.m, jd.degen_n != 0, s);
         }

@@ -16,9 +16,10 @@ namespace ext {
 //           order, Toeplitz: P = N, rot = 0); rot = m gives the paper's order of
 //           eq. toep (Alg. 2's placement v'[i] = y_i for i < m, v'[L-n+1+t] =
 //           y_{m+t}). Dodis/Circulant use P = n, rot = 0: s_k = y_{k mod n}.
-//   REV     (Dodis/Circulant input): i < N ? b'_{N-1-i} : 0 with
+//   REV     (Dodis/Circulant input): i < a ? b'_{N-1-i} : 0 with
 //           b'_j = (j < len ? b_j : 0): the input reversed (Circulant: x' = [x, 0],
-//           len = N - 1).
+//           len = N - 1); a = N for the whole input, a < N for the first piece of
+//           the two-piece schedule (its positions a.. belong to the second piece).
 // Dodis(x, y)_i = XOR_j x_{(j-i) mod n} y_j equals the linear-order Toeplitz
 // extractor of rev(x) with the seed y || y_{0..m-2}: both sides are
 // XOR_{j'} x_{j'} y_{(i+j') mod n}. That needs a transform of length n + m - 1

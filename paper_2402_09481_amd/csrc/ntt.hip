@@ -75,7 +75,7 @@ __host__ __device__ inline uint32_t emb_bit(const Emb &e, uint64_t i, uint64_t L
         if (k >= e.N) return 0u;
         return getbit(e.bits, mod_small(k + e.rot, e.P));
     }
-    if (i >= e.N) return 0u;
+    if (i >= e.a) return 0u;
     const uint64_t j = e.N - 1 - i;
     return j < e.len ? getbit(e.bits, j) : 0u;
 }
@@ -705,16 +705,16 @@ __host__ __device__ inline uint64_t embed_word(const Emb &e, uint64_t L, uint64_
         }
         return out;
     }
-    // REV: position i < N holds b'_{N-1-i}, b'_j = j < len ? b_j : 0
+    // REV: position i < a holds b'_{N-1-i}, b'_j = j < len ? b_j : 0
     for (int t = 0; t < 64;) {
         const uint64_t i = i0 + t;
-        if (i >= e.N) break;
+        if (i >= e.a) break;
         const uint64_t j = e.N - 1 - i;  // positions i.. read j, j-1, ..
         if (j >= e.len) {                // sources beyond len are zero: skip to j = len - 1
             t += (int)umin64(j - e.len + 1, (uint64_t)(64 - t));
             continue;
         }
-        const int run = (int)umin64(64 - t, j + 1);
+        const int run = (int)umin64(umin64(64 - t, j + 1), e.a - i);
         const uint64_t rev = __builtin_bitreverse64(bits_at(e.bits, j - run + 1, run)) >> (64 - run);
         out |= rev << t;
         t += run;

@@ -46,19 +46,24 @@ def test_na_utilities_match_oracle(lib):
 def test_plan_lengths_and_workspace(lib):
     wb = ctypes.c_int32()
     # Toeplitz n = 2^30, m = 2^29 runs as two pieces of 2^29 input bits, each a
-    # transform of 2^30 over 3*2^30+1; Dodis/Circulant beyond 2^30 keep the 64-bit field
+    # transform of 2^30 over 3*2^30+1, and so do Dodis/Circulant shapes whose halves
+    # fit 2^30; shapes whose halves do not keep one transform over the 64-bit field
+    big_na = lib.ext_next_na(1 << 31)
     cases = [(0, 4096, 2048, 8192, 32), (2, 1048589, 1 << 19, 1 << 21, 32), (0, 1 << 30, 1 << 29, 1 << 30, 32),
              (1, 1048588, 1000, 1 << 21, 32), (2, 1048589, 1048589, 1 << 22, 32), (0, 1, 1, 64, 32),
              (0, (1 << 26), (1 << 25), 1 << 27, 32), (0, 1 << 28, 1 << 28, 1 << 29, 32),
-             (2, 1073741827, 1 << 20, 1 << 31, 64), (0, (1 << 31) - 64, 1 << 20, 1 << 32, 64)]
+             (2, 1073741827, 1 << 20, 1 << 30, 32), (1, 1738000138, 23998262, 1 << 30, 32),
+             (0, (1 << 31) - 64, 1 << 20, 1 << 32, 64), (2, big_na, 1000, 1 << 32, 64)]
     for kind, n, m, L, bits in cases:
         assert lib.ext_plan_length(kind, n, m, ctypes.byref(wb)) == L
         assert wb.value == bits
     assert lib.ext_workspace_bytes(0, 4096, 2048) == 0  # one workgroup, no workspace
     big = lib.ext_workspace_bytes(0, 1 << 30, 1 << 29)  # four arrays of 2^30 32-bit words
     assert 4 * (1 << 30) * 4 <= big < 4 * (1 << 30) * 4 + (1 << 30)
-    big = lib.ext_workspace_bytes(2, 1073741827, 1 << 20)  # two arrays of 2^31 64-bit words
-    assert 2 * (1 << 31) * 8 <= big < 2 * (1 << 31) * 8 + (1 << 30)
+    big = lib.ext_workspace_bytes(2, 1073741827, 1 << 20)  # two pieces: four arrays of 2^30 32-bit words
+    assert 4 * (1 << 30) * 4 <= big < 4 * (1 << 30) * 4 + (1 << 30)
+    big = lib.ext_workspace_bytes(2, big_na, 1000)  # one transform: two arrays of 2^32 64-bit words
+    assert 2 * (1 << 32) * 8 <= big < 2 * (1 << 32) * 8 + (1 << 31)
     # invalid shapes
     for kind, n, m in [(0, 10, 0), (0, 10, 11), (1, 10, 11), (2, 5, 6), (7, 10, 5), (0, (1 << 33), 1 << 31)]:
         assert lib.ext_plan_length(kind, n, m, None) == 0
@@ -91,15 +96,15 @@ def test_null_context_calls(lib):
 
 def test_paper_qrng_shapes_exceed_the_largest_transform(lib):
     """The QRNG example (n = 6.5e9) needs a transform longer than 2^32 (the 64-bit
-    field's limit): rejected as too large; the QKD Toeplitz shape runs as two pieces
-    of 2^30 and the Circulant one as one transform of 2^31."""
+    field's limit): rejected as too large; the QKD Toeplitz and Circulant shapes run
+    as two pieces of 2^30 each."""
     import workloads as W
     assert lib.ext_plan_length(0, W.QRNG_N, W.QRNG_M, None) == 0
     n_adj = oracle.closest_na(W.QRNG_N + 1)
     assert lib.ext_plan_length(1, n_adj - 1, 500_000_000, None) == 0
     assert lib.ext_plan_length(0, W.QKD_N, W.QKD_M, None) == 1 << 30
     n_in, m = W.qkd_circulant_shape(oracle.next_na)
-    assert lib.ext_plan_length(1, n_in, m, None) == 1 << 31
+    assert lib.ext_plan_length(1, n_in, m, None) == 1 << 30
 
 
 def test_von_neumann_host_surface(lib):

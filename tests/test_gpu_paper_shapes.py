@@ -1,6 +1,7 @@
 """The paper's QKD privacy-amplification shapes (Toeplitz n = 1.738e9, m = 41,378,264,
-and the improved Circulant variant): sampled output words against the oracle's rows
-and GF(2) bilinearity of the whole output."""
+and the improved Circulant variant, both run as two pieces of 2^30): sampled output
+words against the oracle's rows, GF(2) bilinearity of the whole Toeplitz output, and
+the whole Circulant output against the one 2^31 transform over the 64-bit field."""
 import numpy as np
 import pytest
 
@@ -44,9 +45,13 @@ def test_qkd_improved_circulant():
     ctx = P.Context(0)
     job = W.qkd_circulant(P.next_na_set)
     show_case("qkd circulant", job.n, job.m)
-    z = to_host(ctx.extract("circulant", to_dev(job.x), to_dev(job.y), job.n, job.m, sync=True))
+    x, y = to_dev(job.x), to_dev(job.y)
+    z = to_host(ctx.extract("circulant", x, y, job.n, job.m, sync=True))  # two pieces of 2^30
     for w in sampled_words(z.size, 3):
         cnt = min(64, job.m - 64 * w)
         want = oracle.circulant_rows(job.x, job.y, job.n, job.m, 64 * w, cnt)
         assert int(z[w]) == int(want[0]), w
+    # the whole output equals the one transform of 2^31 over 2^64 - 2^32 + 1
+    z1 = to_host(ctx.extract("circulant", x, y, job.n, job.m, sync=True, single_transform=True))
+    assert np.array_equal(z, z1)
     ctx.close()

@@ -154,6 +154,26 @@ def test_two_piece_schedule(ctx_2p, n, m):
     run_case(ctx_2p, "toeplitz", n, m, "linear", seed=13 * n + m, px=0.3)
 
 
+@pytest.mark.parametrize("kind,n,m", [("dodis", 131, 1), ("dodis", 131, 131), ("dodis", 4099, 2048),
+                                      ("dodis", 65539, 65539), ("dodis", 1048589, 1 << 19), ("circulant", 130, 1),
+                                      ("circulant", 130, 129), ("circulant", 4132, 4000), ("circulant", 65580, 30000)])
+def test_two_piece_dodis_circulant(ctx_2p, kind, n, m):
+    """Dodis and Circulant in their Toeplitz form over the reversed input, split in
+    two pieces (first piece: the reversed input's first a positions with the
+    periodic seed's window from s_(n-a); second: the rest with the window from s_0)."""
+    run_case(ctx_2p, kind, n, m, seed=17 * n + m)
+
+
+def test_two_piece_dodis_degenerate(ctx_2p):
+    n, m = 4099, 100
+    y = W.bernoulli_bits(W.rng(3), n, 0.5)
+    for x in (np.zeros(W.nwords(n), np.uint64), W.mask_tail(np.full(W.nwords(n), ~np.uint64(0)), n)):
+        show_case("two-piece degenerate", int(x[0] & np.uint64(1)))
+        code, z = gpu_extract(ctx_2p, "dodis", x, y, n, m)
+        assert code == oracle.EDEGENERATE
+        assert not z.any()
+
+
 def test_dodis_degenerate_inputs(ctx):
     n, m = 1019, 300
     y = W.bernoulli_bits(W.rng(1), n, 0.5)
