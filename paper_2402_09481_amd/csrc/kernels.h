@@ -54,7 +54,8 @@ struct JobDev {
     uint64_t nfold;    // 0, or n for a wrap-around fold z_i = c_i ^ c_{i+n} (unused by the built-in shapes)
     uint64_t out_len;  // coefficients whose parity is needed: m or m + n
     uint64_t degen_n;  // bits of x checked for all-0/all-1 (Dodis), 0 = no check
-    uint64_t K;        // pointwise constant: folds L^-1 (and Montgomery factors)
+    uint64_t K;        // pointwise constant: folds L^-1 (and Montgomery factors); applied by
+                       // the single-workgroup pass or the last inverse strided pass
 };
 
 struct Tables {
@@ -112,10 +113,11 @@ constexpr int strided_cols(int word_bits, int mode) {
 }
 // Contiguous pass over rows of R = 2^lgr consecutive words (last level).
 // C_FUSED: the seed's last forward level, the product with the input spectrum S
-// (times L^-1) and the first inverse level. Two-piece schedule: C_PROD is the
-// second piece's seed last forward level times its input spectrum S, written back
-// (the piece's product spectrum); C_FUSED2 is C_FUSED of the first piece with
-// that product S2 added before the factor L^-1 and the inverse.
+// and the first inverse level (the factor L^-1, K, is applied by the last
+// inverse pass, S_INV_PARITY). Two-piece schedule: C_PROD is the second piece's
+// seed last forward level times its input spectrum S, written back (the piece's
+// product spectrum); C_FUSED2 is C_FUSED of the first piece with that product
+// S2 added before the inverse.
 enum ContigMode : int { C_FWD = 0, C_FUSED = 1, C_FUSED2 = 2, C_PROD = 3 };
 
 struct PassLaunch {

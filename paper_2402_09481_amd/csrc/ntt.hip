@@ -393,6 +393,10 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
                 const uint64_t col = ct * C + c;
                 wt = twiddle<F>(a.tb, (uint64_t(0) - ((col * (uint64_t)j) << shift)) & emask);
                 st = twiddle<F>(a.tb, (uint64_t(0) - ((col * (uint64_t)(R / RAD)) << shift)) & emask);
+                // the last inverse pass also applies the pointwise constant K (L^-1
+                // and Montgomery factors): one product per group at the start of
+                // its twiddle sequence instead of one per value in the fused pass
+                if constexpr (MODE == S_INV_PARITY) wt = F::tw_combine(wt, (T)J.K);
             }
             // element index of row r = j + t R/RAD, column c: a running sum (one
             // 64-bit add per element instead of a 32x64-bit product)
@@ -502,7 +506,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
     run_steps_from<F, Tl, false, 0>(v, lds, a.tb);
     if constexpr (MODE == C_FUSED || MODE == C_FUSED2) {
         static_assert(Ends<Tl, true>::RAD_FIRST == RADL, "register hand-over needs equal radices");
-        const T K = (T)J.K;
+        // (the constant K is applied by the last inverse pass)
         const T *prod2 = (const T *)J.S2;
 #pragma unroll
         for (int q = 0; q < GPTL; ++q) {
@@ -513,7 +517,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
                 const uint64_t gi = base + (uint64_t)c * R + j + t * (R / RADL);
                 T prod = F::mont(v[q * RADL + t], spec[gi]);
                 if constexpr (MODE == C_FUSED2) prod = F::add(prod, F::as_b(prod2[gi]));
-                v[q * RADL + t] = F::mont(prod, K);
+                v[q * RADL + t] = prod;
             }
         }
         __syncthreads();  // LDS is reused by the inverse steps
