@@ -10,11 +10,15 @@ input bits to packed output bits).
 Printed as one JSON line (rank 0). Besides the headline it reports:
   roofline      the dominant kernel's algorithmic bytes / its average duration
                 (HIP events around every launch, on the launch stream, during
-                the timed steps) against the 8 TB/s HBM peak;
+                the timed steps) against the 8 TB/s HBM peak, with measured
+                traffic, its VALU view and the binding one of the two;
   path          the whole step's algorithmic bytes (the two-pass lower bound of
                 10 L w + packed I/O) / step time;
   cpu_baseline  the oracle (plain schoolbook GF(2) rows, one thread) timed on a
                 bounded sample of the same workload, scaled to Mbit/s;
+  cpu_ntt       a single-threaded CPU NTT convolution, scaled to the headline;
+  small_configs the small Toeplitz workload's call latency (p50/p99) and the
+                Dodis workload's time per call (skip with --no-small);
   --batched     the 4096-block batched workload: extract_batch vs one call
                 sequence per block on the same GPU;
   --serving     a short open-loop Poisson serving run (p50/p99 latency).
@@ -478,6 +482,66 @@ def run_von_neumann(log, reps=10, oracle_bits=1 << 27):
     return out
 
 
+def run_small_configs(log, calls=10000):
+    """The two small workloads: Toeplitz n = 4096, m = 2048 (linear seed order; one
+    workgroup, latency-bound) as the host-measured latency of one synchronous call,
+    p50/p99 over `calls` calls, plus the device time per call back to back; and the
+    Dodis workload (n = 1,048,589, m = 2^19) as milliseconds per call from HIP
+    events over 20 calls."""
+    import numpy as np
+    import torch
+
+    import paper_2402_09481_amd as P
+    import workloads as W
+
+    ctx = P.Context(0)
+    stream = torch.cuda.current_stream()
+    out = {}
+    j = W.toeplitz_small()
+    x = torch.from_numpy(j.x.view(np.int64)).cuda()
+    y = torch.from_numpy(j.y.view(np.int64)).cuda()
+    z = torch.empty(P.words(j.m), dtype=torch.int64, device="cuda")
+    for _ in range(200):
+        ctx.extract("toeplitz", x, y, j.n, j.m, z=z, seed_order="linear", sync=True)
+    log("small configs: %d synchronous calls" % calls)
+    lat = np.empty(calls)
+    for i in range(calls):
+        t0 = time.perf_counter()
+        ctx.extract("toeplitz", x, y, j.n, j.m, z=z, seed_order="linear", sync=True)
+        lat[i] = time.perf_counter() - t0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(1000):
+        ctx.extract("toeplitz", x, y, j.n, j.m, z=z, seed_order="linear", stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dev_us = e0.elapsed_time(e1) * 1e3 / 1000
+    out["toeplitz_4096"] = {"n": j.n, "m": j.m, "calls": calls,
+                            "sync_call_us": {"p50": round(float(np.percentile(lat, 50)) * 1e6, 2),
+                                             "p99": round(float(np.percentile(lat, 99)) * 1e6, 2),
+                                             "mean": round(float(lat.mean()) * 1e6, 2)},
+                            "back_to_back_us_per_call": round(dev_us, 2),
+                            "output_Mbit_s_back_to_back": round(j.m / (dev_us * 1e-6) / 1e6, 1)}
+    d = W.dodis_2p20()
+    x = torch.from_numpy(d.x.view(np.int64)).cuda()
+    y = torch.from_numpy(d.y.view(np.int64)).cuda()
+    z = torch.empty(P.words(d.m), dtype=torch.int64, device="cuda")
+    for _ in range(3):
+        ctx.extract("dodis", x, y, d.n, d.m, z=z, sync=True)
+    e0.record(stream)
+    for _ in range(20):
+        ctx.extract("dodis", x, y, d.n, d.m, z=z, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    out["dodis_1048589"] = {"n": d.n, "m": d.m, "ms_per_call": round(ms, 4),
+                            "output_Mbit_s": round(d.m / (ms * 1e-3) / 1e6, 1),
+                            "transform_length": int(ctx._lib.ext_plan_length(P.EXT_KIND_DODIS, d.n, d.m, None))}
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -491,6 +555,8 @@ def main():
     ap.add_argument("--von-neumann", action="store_true", help="also time the Von Neumann extractor")
     ap.add_argument("--two-piece", action="store_true",
                     help="also time the headline shape with the default two-piece plan")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small Toeplitz latency and Dodis timing (run by default, about a second)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="run a plain device copy of this many GiB first (reference for byte counters)")
     args = ap.parse_args()
@@ -516,6 +582,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(job, args.cpu_seconds)
         log("cpu NTT baseline (one thread)")
         out["cpu_ntt"] = cpu_ntt_baseline()
+    if not args.no_small:
+        out["small_configs"] = run_small_configs(log)
     if args.batched:
         out["batched"] = run_batched(log)
     if args.paper_shapes:
