@@ -99,11 +99,12 @@ struct FP0 {
     static constexpr int WORD_BITS = 32;
 
     // a, b in [0, P): a + b < 2P may carry out of 32 bits; the result is
-    // a + b - P when it carried or reached P, else a + b.
+    // a + b - P when it carried or reached P (no borrow in s - P), else a + b.
     __device__ static inline uint32_t add(uint32_t a, uint32_t b) {
-        uint32_t s;
+        uint32_t s, t;
         const bool c = __builtin_add_overflow(a, b, &s);
-        return (c || s >= P) ? s - P : s;
+        const bool below = __builtin_sub_overflow(s, P, &t);
+        return (c || !below) ? t : s;
     }
     // the borrow of a - b selects the correction (written out, so that operands
     // known to be high halves of products are not compared as 64-bit values)
