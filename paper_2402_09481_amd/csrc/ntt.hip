@@ -58,6 +58,18 @@ __host__ __device__ inline uint64_t umin64(uint64_t a, uint64_t b) { return a < 
 template <int C>
 using UnitOf = typename std::conditional<C == 8, uint8_t, typename std::conditional<C == 16, uint16_t, uint32_t>::type>::type;
 
+// Loads and stores through the global address space. A pointer read from a job
+// descriptor is otherwise a flat access, which also counts against the LDS wait
+// counter, so that every barrier (which waits for LDS) would wait for it too.
+template <class T>
+__device__ inline T gload(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ inline void gstore(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
 __host__ __device__ inline uint32_t getbit(const uint64_t *b, uint64_t i) {
     return (uint32_t)(b[i >> 6] >> (i & 63)) & 1u;
 }
@@ -142,6 +154,52 @@ __device__ inline typename F::T twiddle(const Tables &tb, uint64_t E) {
 
 // ------------------------------------------------------------------ tile geometry
 
+// Radix of step s of a 2^lgr-point transform done in radix-16 Stockham steps
+// plus one leftover radix RF. A step of radix r multiplies (r-1)/r of its
+// values by twiddles, except the first step, which has none; so RF is best
+// anywhere but first (9 levels: 16*2*16 takes 1/2 + 15/16 twiddle products per
+// value where 2*16*16 takes 15/16 + 15/16). ORDER 1: RF second in both
+// directions; ORDER 2: RF second in the forward and last in the inverse (the
+// fused pass: as cheap, and fewer registers); ORDER 0: RF first in the forward
+// and last in the inverse. With two steps the forward order is always RF, 16
+// and the inverse 16, RF, so that a fused pass hands the forward's last
+// radix-16 layout to the inverse's first step. Every order gives the same
+// transform in the same (natural) order.
+__host__ __device__ constexpr int step_radix(int lgr, int order, int s, bool inv) {
+    const int rf = (lgr % 4) ? (1 << (lgr % 4)) : 16, nsteps = (lgr + 3) / 4;
+    if (nsteps >= 3 && (order == 1 || (order == 2 && !inv))) return s == 1 ? rf : 16;
+    if (nsteps >= 2) return inv ? (s == nsteps - 1 ? rf : 16) : (s == 0 ? rf : 16);
+    return rf;
+}
+__host__ __device__ constexpr int step_span(int lgr, int order, int s, bool inv) {
+    int ns = 1;
+    for (int i = 0; i < s; ++i) ns *= step_radix(lgr, order, i, inv);
+    return ns;
+}
+// Stockham twiddles of one direction's steps as the strided kernel keeps them
+// in LDS: the block of step s >= 1 ((radix - 1) span words, laid out as the
+// global block) at step_twiddle_off(s); step 0 has none.
+__host__ __device__ constexpr int step_twiddle_off(int lgr, int order, int s, bool inv) {
+    int o = 0;
+    for (int i = 1; i < s; ++i) o += (step_radix(lgr, order, i, inv) - 1) * step_span(lgr, order, i, inv);
+    return o;
+}
+__host__ __device__ constexpr int step_twiddle_words(int lgr, int order) {
+    const int nsteps = (lgr + 3) / 4;
+    const int f = step_twiddle_off(lgr, order, nsteps, false), i = step_twiddle_off(lgr, order, nsteps, true);
+    return f > i ? f : i;
+}
+
+// Whether a strided pass keeps the next tile's loads in flight: the inverse
+// passes of the 64-bit field's 256- and 512-row columns, where the registers
+// allow it without spilling (4 waves per SIMD). Measured at 512 rows: the two
+// inverse passes 4% and 8% faster; the forward passes slower (bits 13%, values
+// 3%), so they, and everything else, run one workgroup per tile with the
+// Stockham twiddles read from the global blocks.
+__host__ __device__ constexpr bool strided_prefetch(int word_bits, int lgr, int mode) {
+    return word_bits == 64 && (lgr == 8 || lgr == 9) && (mode == S_INV || mode == S_INV_PARITY);
+}
+
 template <class F, int LGR, bool STRIDED, int ORDER = 1, int SMODE = S_FWD_BITS>
 struct Tile {
     using T = typename F::T;
@@ -156,9 +214,21 @@ struct Tile {
     static_assert(EPT >= 16 && EPT % 16 == 0, "tile too small");
     static_assert(NT % 64 == 0 || NT < 64, "whole waves");
 
+    __host__ __device__ static constexpr int radix(int s, bool inv) { return step_radix(LGR, ORDER, s, inv); }
+    __host__ __device__ static constexpr int span(int s, bool inv) { return step_span(LGR, ORDER, s, inv); }
+    __host__ __device__ static constexpr int stw_off(int s, bool inv) { return step_twiddle_off(LGR, ORDER, s, inv); }
+    // LDS offset of the twiddle block of the step with radix rad and span ns
+    __host__ __device__ static constexpr int stw_block(int rad, int ns, bool inv) {
+        for (int i = 1; i < NSTEPS; ++i)
+            if (radix(i, inv) == rad && span(i, inv) == ns) return stw_off(i, inv);
+        return 0;
+    }
+    static constexpr bool PF = STRIDED && strided_prefetch(F::WORD_BITS, LGR, SMODE);
+    static constexpr int STW_WORDS = PF ? step_twiddle_words(LGR, ORDER) : 0;
+
     // contiguous tiles pad one word per 16 so that power-of-two strides spread over banks
     static constexpr int RP = STRIDED ? R : R + R / 16;
-    static constexpr int LDS_WORDS = STRIDED ? C * R : C * RP;
+    static constexpr int LDS_WORDS = STRIDED ? C * R + STW_WORDS : C * RP;
     // Waves per SIMD that strided kernels promise the register allocator: as
     // many as the LDS admits (160 KiB per CU, 4 SIMDs), at most 8. A register
     // count above that would leave LDS idle and halve the resident workgroups
@@ -179,34 +249,19 @@ struct Tile {
             c = g / (R / RAD);
         }
     }
-    // Radix of step s. A step of radix r multiplies (r-1)/r of its values by
-    // twiddles, except the first step, which has none; so the leftover radix RF
-    // is best anywhere but first (9 levels: 16*2*16 takes 1/2 + 15/16 twiddle
-    // products per value where 2*16*16 takes 15/16 + 15/16). ORDER 1: RF second
-    // in both directions; ORDER 2: RF second in the forward and last in the
-    // inverse (the fused pass: as cheap, and fewer registers); ORDER 0: RF first
-    // in the forward and last in the inverse. With two steps the forward order
-    // is always RF, 16 and the inverse 16, RF, so that a fused pass hands the
-    // forward's last radix-16 layout to the inverse's first step. Every order
-    // gives the same transform in the same (natural) order.
-    __host__ __device__ static constexpr int radix(int s, bool inv) {
-        if (NSTEPS >= 3 && (ORDER == 1 || (ORDER == 2 && !inv))) return s == 1 ? RF : 16;
-        if (NSTEPS >= 2) return inv ? (s == NSTEPS - 1 ? RF : 16) : (s == 0 ? RF : 16);
-        return RF;
-    }
-    __host__ __device__ static constexpr int span(int s, bool inv) {
-        int ns = 1;
-        for (int i = 0; i < s; ++i) ns *= radix(i, inv);
-        return ns;
-    }
 };
 
 // Stockham step compute on registers v (EPT values = EPT/RAD groups of RAD).
-template <class F, class Tl, int RAD, int NS, bool INV>
-__device__ inline void step_compute(typename F::T *v, const Tables &tb) {
+// Twiddles from the global blocks, or (LT) from the tile's LDS copy stw.
+template <class F, class Tl, int RAD, int NS, bool INV, bool LT = false>
+__device__ inline void step_compute(typename F::T *v, const Tables &tb, const typename F::T *stw = nullptr) {
     using T = typename F::T;
     static_assert(NS * RAD <= (1 << TWIN_LG) && RAD <= 16, "step beyond the Stockham twiddle blocks");
-    const T *tw = (const T *)tb.stk + stk_offset(RAD, NS, INV);
+    const T *tw;
+    if constexpr (LT)
+        tw = stw + Tl::stw_block(RAD, NS, INV);
+    else
+        tw = (const T *)tb.stk + stk_offset(RAD, NS, INV);
     constexpr int GPT = Tl::EPT / RAD;
 #pragma unroll
     for (int q = 0; q < GPT; ++q) {
@@ -308,8 +363,9 @@ __device__ inline void run_steps_pre(typename F::T *v, typename F::T *lds, const
 // Run steps [s0, s1) of a transform whose inputs for step s0 are already in
 // registers; the outputs of step s1-1 stay in registers (positions of the
 // last-step layout if s1 == NSTEPS). LDS exchanges in between.
-template <class F, class Tl, bool INV, int S, bool PRE = false>
-__device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, const Tables &tb) {
+template <class F, class Tl, bool INV, int S, bool PRE = false, bool LT = false>
+__device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, const Tables &tb,
+                                      const typename F::T *stw = nullptr) {
     if constexpr (S == 0 && PRE) {
         typename F::T tw0[Tl::EPT];  // the first step has no twiddles
         run_steps_pre<F, Tl, INV, 0>(v, lds, tb, tw0);
@@ -320,12 +376,12 @@ __device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, cons
             // inputs of this step come from LDS, written by the previous step
             step_load_lds<F, Tl, RAD>(v, lds);
         }
-        step_compute<F, Tl, RAD, NS, INV>(v, tb);
+        step_compute<F, Tl, RAD, NS, INV, LT>(v, tb, stw);
         if constexpr (S + 1 < Tl::NSTEPS) {
             __syncthreads();  // every read of the previous layout is done
             step_store_lds<F, Tl, RAD>(v, lds, NS);
             __syncthreads();
-            run_steps_from<F, Tl, INV, S + 1>(v, lds, tb);
+            run_steps_from<F, Tl, INV, S + 1, false, LT>(v, lds, tb, stw);
         }
     }
 }
@@ -339,14 +395,21 @@ struct Ends {
 // ------------------------------------------------------------------ strided pass
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2 and address
-// translation cache) round-robin by index. Tile = this remap of the index gives
-// every XCD one contiguous run of tiles, so neighbouring column groups (the same
-// rows, the same memory pages) are read through the same L2. A bijection when
-// the grid is a multiple of 8, the identity otherwise.
-__device__ inline uint64_t xcd_tile(uint64_t b, uint64_t nb) {
+// translation cache) round-robin by index. The k-th tile of workgroup b of a
+// grid of W (tiles b, b + W, ... in order, ~0 past the n tiles) is, for the
+// value passes (remap), chosen so that every XCD runs through one contiguous
+// run of n/8 tiles, so neighbouring column groups (the same rows, the same
+// memory pages) are read through the same L2. The remap needs W and n to be
+// multiples of 8; otherwise, and for the other passes, tile b + k W.
+constexpr uint64_t NO_TILE = ~uint64_t(0);
+__device__ inline uint64_t tile_seq(uint64_t b, uint64_t W, uint64_t k, uint64_t n, bool remap) {
     constexpr uint64_t XCDS = 8;
-    if (nb % XCDS) return b;
-    return (b % XCDS) * (nb / XCDS) + b / XCDS;
+    if (remap && W % XCDS == 0 && n % XCDS == 0) {
+        const uint64_t i = b / XCDS + k * (W / XCDS), chunk = n / XCDS;
+        return i < chunk ? (b % XCDS) * chunk + i : NO_TILE;
+    }
+    const uint64_t t = b + k * W;
+    return t < n ? t : NO_TILE;
 }
 
 struct KArgs {
@@ -354,112 +417,192 @@ struct KArgs {
     JobDev one;
     Tables tb;
     uint64_t S, Mprev;
-    int which;  // array read and written (0: A, 1: B)
+    uint64_t tiles;  // tiles per job
+    int which;       // array read and written (0: A, 1: B)
 };
 
+// A strided pass. With prefetch it is persistent: each workgroup runs through
+// its tiles in order and issues the next tile's loads (values, or bit units,
+// and the table words of its inverse twiddles) before it transforms the
+// current one, so that HBM latency overlaps the arithmetic. The Stockham
+// twiddles of the column transform stay in LDS beside the tile.
 template <class F, int LGR, int MODE>
 __global__ void __launch_bounds__((Tile<F, LGR, true, 1, MODE>::NT))
 __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))) k_strided(KArgs a) {
     using Tl = Tile<F, LGR, true, 1, MODE>;
     using T = typename F::T;
-    constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
+    constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT, NT = Tl::NT;
     constexpr bool INV = (MODE == S_INV || MODE == S_INV_PARITY);
+    constexpr bool FWD = !INV;
+    constexpr bool BITS = MODE == S_FWD_BITS;
+    constexpr int RF = Ends<Tl, INV>::RAD_FIRST, GF = EPT / RF;
+    constexpr int RL = Ends<Tl, INV>::RAD_LAST, GL = EPT / RL;
+    constexpr bool PF = Tl::PF;
     using Unit = UnitOf<C>;
+    using X = typename std::conditional<BITS, uint32_t, T>::type;
     __shared__ T lds[C * R];
+    __shared__ T stw[Tl::STW_WORDS > 0 ? Tl::STW_WORDS : 1];
 
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
     T *data = (T *)(a.which ? J.B : J.A);
+    const Unit *ub = (const Unit *)J.eb[a.which];
+    // (the descriptor is read once: the tile stores could alias it)
+    Unit *const par = (Unit *)J.eb[0];
+    const T Kc = (T)J.K;
+    const T *thi = (const T *)a.tb.hi, *tlo = (const T *)a.tb.lo;
     const uint64_t colTiles = a.S / C;
-    // (measured: the remap helps the value passes and slows the bit-reading first
-    // forward pass)
-    const uint64_t tile = (MODE == S_FWD || MODE == S_INV) ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-    const uint64_t blk = tile / colTiles, ct = tile - blk * colTiles;
-    const uint64_t base = blk * a.Mprev + ct * C;
     const int shift = F::LGMAX - (63 - __builtin_clzll(a.Mprev));  // 2^LGMAX / Mprev = 2^shift
     const uint64_t emask = (uint64_t(1) << F::LGMAX) - 1;
+    // (measured: the remap helps the value passes and slows the bit-reading first
+    // forward pass)
+    constexpr bool REMAP = (MODE == S_FWD || MODE == S_INV);
+    const uint64_t W = gridDim.x, b = blockIdx.x;
 
-    T v[EPT];
-    {
-        constexpr int RAD = Ends<Tl, INV>::RAD_FIRST;
-        constexpr int GPT = EPT / RAD;
+    uint64_t tile = tile_seq(b, W, 0, a.tiles, REMAP);
+    if (tile == NO_TILE) return;
+    if constexpr (PF) {
+        for (int s = 1; s < Tl::NSTEPS; ++s) {
+            const int rad = Tl::radix(s, INV), ns = Tl::span(s, INV);
+            const T *src = (const T *)a.tb.stk + stk_offset(rad, ns, INV);
+            for (int i = threadIdx.x; i < (rad - 1) * ns; i += NT) stw[Tl::stw_off(s, INV) + i] = gload(src + i);
+        }
+    }
+
+    // loads of a tile in the first step's layout: group q of thread (c, j) holds
+    // rows j + t R/RF of column c; the inverse twiddle w^-(col r) of those rows is
+    // a geometric sequence in t, from two table twiddles (four table words)
+    X xr[EPT];
+    T tr[INV ? 4 * GF : 1];
+    auto issue = [&](uint64_t tl) {
+        const uint64_t blk = tl / colTiles, ct = tl - blk * colTiles;
+        const uint64_t base = blk * a.Mprev + ct * C;
 #pragma unroll
-        for (int q = 0; q < GPT; ++q) {
+        for (int q = 0; q < GF; ++q) {
             int c, j;
-            Tl::template coords<RAD>(q, c, j);
-            // inverse: twiddle w^-(col r) for rows r = j + t R/RAD, a geometric
-            // sequence in t: two table twiddles per group, then products
-            T wt = T(), st = T();
+            Tl::template coords<RF>(q, c, j);
             if constexpr (INV) {
                 const uint64_t col = ct * C + c;
-                wt = twiddle<F>(a.tb, (uint64_t(0) - ((col * (uint64_t)j) << shift)) & emask);
-                st = twiddle<F>(a.tb, (uint64_t(0) - ((col * (uint64_t)(R / RAD)) << shift)) & emask);
+                const uint64_t ew = (uint64_t(0) - ((col * (uint64_t)j) << shift)) & emask;
+                const uint64_t es = (uint64_t(0) - ((col * (uint64_t)(R / RF)) << shift)) & emask;
+                tr[4 * q] = gload(thi + (ew >> 16));
+                tr[4 * q + 1] = gload(tlo + (ew & 0xFFFF));
+                tr[4 * q + 2] = gload(thi + (es >> 16));
+                tr[4 * q + 3] = gload(tlo + (es & 0xFFFF));
+            }
+            // element index of row r = j + t R/RF, column c: a running sum (one
+            // 64-bit add per element instead of a 32x64-bit product)
+            const uint64_t rstep = (uint64_t)(R / RF) * a.S;
+            uint64_t gi = base + (uint64_t)j * a.S + c;
+#pragma unroll
+            for (int t = 0; t < RF; ++t, gi += rstep) {
+                // bits: a row segment of the tile is C adjacent bits starting at a
+                // multiple of C, one C-bit unit, the same address for every lane
+                // of the row
+                if constexpr (BITS)
+                    xr[q * RF + t] = gload(ub + (gi - c) / C);
+                else
+                    xr[q * RF + t] = gload(data + gi);
+            }
+        }
+    };
+
+    // the issued loads of a tile as the first step's values (inverse: times their
+    // twiddles)
+    auto finish = [&](T *v) {
+#pragma unroll
+        for (int q = 0; q < GF; ++q) {
+            int c, j;
+            Tl::template coords<RF>(q, c, j);
+            T wt = T(), st = T();
+            if constexpr (INV) {
+                wt = F::tw_combine(tr[4 * q], tr[4 * q + 1]);
+                st = F::tw_combine(tr[4 * q + 2], tr[4 * q + 3]);
                 // the last inverse pass also applies the pointwise constant K (L^-1
                 // and Montgomery factors): one product per group at the start of
                 // its twiddle sequence instead of one per value in the fused pass
-                if constexpr (MODE == S_INV_PARITY) wt = F::tw_combine(wt, (T)J.K);
+                if constexpr (MODE == S_INV_PARITY) wt = F::tw_combine(wt, Kc);
             }
-            // element index of row r = j + t R/RAD, column c: a running sum (one
-            // 64-bit add per element instead of a 32x64-bit product)
-            const uint64_t rstep = (uint64_t)(R / RAD) * a.S;
-            uint64_t gi = base + (uint64_t)j * a.S + c;
 #pragma unroll
-            for (int t = 0; t < RAD; ++t, gi += rstep) {
+            for (int t = 0; t < RF; ++t) {
                 T x;
-                if constexpr (MODE == S_FWD_BITS) {
-                    // a row segment of the tile is C adjacent bits starting at a
-                    // multiple of C: one C-bit unit, the same address for every
-                    // lane of the row
-                    const Unit *ub = (const Unit *)J.eb[a.which];
-                    x = F::from_bit((uint32_t)(ub[(gi - c) / C] >> c) & 1u);
-                } else {
-                    x = data[gi];
-                }
+                if constexpr (BITS)
+                    x = F::from_bit((xr[q * RF + t] >> c) & 1u);
+                else
+                    x = xr[q * RF + t];
                 if constexpr (INV) {
                     x = F::mul_tw(x, wt);
-                    if (t + 1 < RAD) wt = F::tw_combine(wt, st);
+                    if (t + 1 < RF) wt = F::tw_combine(wt, st);
                 }
-                v[q * RAD + t] = x;
+                v[q * RF + t] = x;
             }
         }
-    }
-    run_steps_from<F, Tl, INV, 0, (F::WORD_BITS == 64 && LGR <= 9)>(v, lds, a.tb);
-    {
-        constexpr int RAD = Ends<Tl, INV>::RAD_LAST;
-        constexpr int GPT = EPT / RAD;
+    };
+
+    T v[EPT];
+    issue(tile);
+    finish(v);
+    if constexpr (PF) {
+        // the first tile's values in registers before the loop (a forward pass takes
+        // them as loaded: without this use the loop would start with a wait for every
+        // memory operation in flight)
 #pragma unroll
-        for (int q = 0; q < GPT; ++q) {
+        for (int i = 0; i < EPT; ++i) asm volatile("" : "+v"(v[i]));
+        __syncthreads();  // the twiddles staged in LDS
+    }
+    // Each round: (prefetch) the next tile's loads, this tile's column transform
+    // and stores, then the next tile's values from its loads. The values are
+    // taken at the end of the round, so the loop never starts by waiting for
+    // memory operations that are still in flight.
+    for (uint64_t k = 1;; ++k) {
+        const uint64_t next = PF ? tile_seq(b, W, k, a.tiles, REMAP) : NO_TILE;
+        if constexpr (PF) {
+            if (next != NO_TILE) issue(next);
+        }
+
+        const uint64_t blk = tile / colTiles, ct = tile - blk * colTiles;
+        const uint64_t base = blk * a.Mprev + ct * C;
+        // without the LDS copy, the 64-bit field's steps load their twiddles one step
+        // early (registers are free up to 128 at 4 waves per SIMD)
+        run_steps_from<F, Tl, INV, 0, (!PF && F::WORD_BITS == 64 && LGR <= 9), PF>(v, lds, a.tb, stw);
+#pragma unroll
+        for (int q = 0; q < GL; ++q) {
             int c, j;
-            Tl::template coords<RAD>(q, c, j);
+            Tl::template coords<RL>(q, c, j);
             // forward: twiddle w^(col r), the same geometric sequence in t
             T wt = T(), st = T();
-            if constexpr (MODE == S_FWD || MODE == S_FWD_BITS) {
+            if constexpr (FWD) {
                 const uint64_t col = ct * C + c;
-                wt = twiddle<F>(a.tb, ((col * (uint64_t)j) << shift) & emask);
-                st = twiddle<F>(a.tb, ((col * (uint64_t)(R / RAD)) << shift) & emask);
+                const uint64_t ew = ((col * (uint64_t)j) << shift) & emask;
+                const uint64_t es = ((col * (uint64_t)(R / RL)) << shift) & emask;
+                wt = F::tw_combine(gload(thi + (ew >> 16)), gload(tlo + (ew & 0xFFFF)));
+                st = F::tw_combine(gload(thi + (es >> 16)), gload(tlo + (es & 0xFFFF)));
             }
-            const uint64_t rstep = (uint64_t)(R / RAD) * a.S;
+            const uint64_t rstep = (uint64_t)(R / RL) * a.S;
             uint64_t gi = base + (uint64_t)j * a.S + c;
 #pragma unroll
-            for (int t = 0; t < RAD; ++t, gi += rstep) {
-                const int r = j + t * (R / RAD);
-                T x = v[q * RAD + t];
-                if constexpr (MODE == S_FWD || MODE == S_FWD_BITS) {
-                    data[gi] = F::mul_tw(x, wt);
-                    if (t + 1 < RAD) wt = F::tw_combine(wt, st);
+            for (int t = 0; t < RL; ++t, gi += rstep) {
+                const int r = j + t * (R / RL);
+                T x = v[q * RL + t];
+                if constexpr (FWD) {
+                    gstore(data + gi, F::mul_tw(x, wt));
+                    if (t + 1 < RL) wt = F::tw_combine(wt, st);
                 } else if constexpr (MODE == S_INV) {
-                    data[gi] = x;
+                    gstore(data + gi, x);
                 } else {
                     // level 0 of the inverse: gi is the coefficient index; the C lanes
                     // of a row hold C consecutive coefficients. Their parities go out
                     // tile-major (unit (ct, r) at ct*R + r, contiguous per workgroup);
                     // a transpose kernel turns that into packed natural order.
-                    uint32_t b = (uint32_t)(F::canon(x) & 1u);
-                    uint64_t mask = __ballot(b);
+                    uint32_t bit = (uint32_t)(F::canon(x) & 1u);
+                    uint64_t mask = __ballot(bit);
                     const int lane = (int)(threadIdx.x & 63);
-                    if (c == 0) ((Unit *)J.eb[0])[ct * R + r] = (Unit)(mask >> (lane & ~(C - 1)));
+                    if (c == 0) gstore(par + ct * R + r, (Unit)(mask >> (lane & ~(C - 1))));
                 }
             }
         }
+        if (next == NO_TILE) break;
+        finish(v);
+        tile = next;
     }
 }
 
@@ -868,13 +1011,27 @@ static KArgs make_args(const PassLaunch &p, const Tables &t) {
     ka.S = p.S;
     ka.Mprev = p.Mprev;
     ka.which = p.which;
+    ka.tiles = p.tiles;
     return ka;
 }
 
+// Workgroups of a strided pass per job: with prefetch, as many as the CUs hold
+// at once (256 CUs, the workgroups per CU that LDS admits; a multiple of 8), at
+// most one per tile; without, one per tile.
+constexpr uint64_t DEVICE_CUS = 256;
+template <class Tl>
+static unsigned strided_grid(uint64_t tiles) {
+    if (!Tl::PF) return (unsigned)tiles;
+    const uint64_t w = DEVICE_CUS * (uint64_t)(Tl::WG_BY_LDS > 0 ? Tl::WG_BY_LDS : 1);
+    return (unsigned)(tiles <= w ? tiles : w);
+}
+
 template <class F, int LGR>
-static hipError_t strided_one(const PassLaunch &p, const KArgs &ka, hipStream_t s) {
-    dim3 grid((unsigned)p.tiles, p.njobs);
-#define L1(M) hipLaunchKernelGGL((k_strided<F, LGR, M>), grid, dim3(Tile<F, LGR, true, 1, M>::NT), 0, s, ka)
+static hipError_t strided_one(const PassLaunch &p, const KArgs &ka0, hipStream_t s) {
+    const KArgs &ka = ka0;
+#define L1(M)                                                                                    \
+    hipLaunchKernelGGL((k_strided<F, LGR, M>), dim3(strided_grid<Tile<F, LGR, true, 1, M>>(p.tiles), p.njobs), \
+                       dim3(Tile<F, LGR, true, 1, M>::NT), 0, s, ka)
     switch (p.mode) {
         case S_FWD_BITS: L1(S_FWD_BITS); break;
         case S_FWD: L1(S_FWD); break;
