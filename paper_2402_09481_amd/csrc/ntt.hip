@@ -629,7 +629,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             int c, j;
             Tl::template coords<RAD>(q, c, j);
 #pragma unroll
-            for (int t = 0; t < RAD; ++t) v[q * RAD + t] = data[base + (uint64_t)c * R + j + t * (R / RAD)];
+            for (int t = 0; t < RAD; ++t) v[q * RAD + t] = gload(data + base + (uint64_t)c * R + j + t * (R / RAD));
         }
     }
     constexpr int RADL = Ends<Tl, false>::RAD_LAST;
@@ -643,7 +643,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             int c, j;
             Tl::template coords<RADL>(q, c, j);
 #pragma unroll
-            for (int t = 0; t < RADL; ++t) sv[q * RADL + t] = spec[base + (uint64_t)c * R + j + t * (R / RADL)];
+            for (int t = 0; t < RADL; ++t) sv[q * RADL + t] = gload(spec + base + (uint64_t)c * R + j + t * (R / RADL));
         }
     }
     run_steps_from<F, Tl, false, 0>(v, lds, a.tb);
@@ -658,8 +658,8 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
 #pragma unroll
             for (int t = 0; t < RADL; ++t) {
                 const uint64_t gi = base + (uint64_t)c * R + j + t * (R / RADL);
-                T prod = F::mont(v[q * RADL + t], spec[gi]);
-                if constexpr (MODE == C_FUSED2) prod = F::add(prod, F::as_b(prod2[gi]));
+                T prod = F::mont(v[q * RADL + t], gload(spec + gi));
+                if constexpr (MODE == C_FUSED2) prod = F::add(prod, F::as_b(gload(prod2 + gi)));
                 v[q * RADL + t] = prod;
             }
         }
@@ -671,7 +671,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             int c, j;
             Tl::template coords<RADI>(q, c, j);
 #pragma unroll
-            for (int t = 0; t < RADI; ++t) data[base + (uint64_t)c * R + j + t * (R / RADI)] = v[q * RADI + t];
+            for (int t = 0; t < RADI; ++t) gstore(data + base + (uint64_t)c * R + j + t * (R / RADI), v[q * RADI + t]);
         }
     } else {
 #pragma unroll
@@ -682,9 +682,9 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             for (int t = 0; t < RADL; ++t) {
                 const uint64_t gi = base + (uint64_t)c * R + j + t * (R / RADL);
                 if constexpr (MODE == C_PROD)
-                    data[gi] = F::mont(v[q * RADL + t], sv[q * RADL + t]);
+                    gstore(data + gi, F::mont(v[q * RADL + t], sv[q * RADL + t]));
                 else
-                    data[gi] = v[q * RADL + t];
+                    gstore(data + gi, v[q * RADL + t]);
             }
         }
     }
