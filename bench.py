@@ -52,14 +52,14 @@ def kernel_bytes(label: str, L: int, w: int, n: int, N: int, m: int) -> int:
     L, contiguous mode 2 (first piece's fused pass plus that product) reads 3L, writes L;
     strided mode 3
     (last inverse pass): reads L words, writes m parity bits; pack: m bits in, m bits out;
-    embed: both packed inputs in, both L-bit coefficient strings out; ptrans: L parity bits
-    in and out."""
+    embed: both packed inputs in, both L-bit coefficient strings out; ptrans: the parity
+    bits of the m output coefficients in and out."""
     if label.startswith("pack"):
         return 2 * (m // 8)
     if label.startswith("embed"):  # both packed inputs in, two L-bit coefficient strings out
         return (n + N) // 8 + 2 * (L // 8)
-    if label.startswith("ptrans"):  # L parity bits, tile-major in, natural order out
-        return 2 * (L // 8)
+    if label.startswith("ptrans"):  # the parity bits of the m output coefficients, in and out
+        return 2 * (m // 8)
     kind = label.split("[")[0]
     fields = dict(kv.split("=") for kv in label.split("[")[1].rstrip("]").split(",")[1:])
     mode, arr = int(fields["mode"]), int(fields.get("arr", 0))

@@ -744,7 +744,11 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         if (e != hipSuccess) return e;
     }
     if (ph == PH_SEED_ONLY || ph == PH_FWD_BOTH) return hipSuccess;
-    // inverse: strided levels backwards; level 0 writes packed parity
+    // inverse: strided levels backwards; level 0 writes packed parity. The output
+    // length out_len is m for every shape built here (batch descriptors included);
+    // a single job's own out_len is honoured as well.
+    const uint64_t max_out = one ? std::max<uint64_t>(max_m, one->out_len) : max_m;
+    uint64_t out_rows = 0;
     std::vector<uint64_t> mp(p.nlev);
     uint64_t M = L;
     for (int i = 0; i < p.nlev; ++i) {
@@ -761,6 +765,10 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         pl.Mprev = mp[i];
         pl.S = mp[i] >> p.lgr[i];
         pl.tiles = (L / mp[i]) * (pl.S / g.C);
+        // level 0: coefficient r S + c sits in row r, and only the coefficients below
+        // the output length are read back
+        pl.out_rows = std::min<uint64_t>((max_out + pl.S - 1) / pl.S, uint64_t(1) << p.lgr[i]);
+        if (i == 0) out_rows = pl.out_rows;
         pl.njobs = njobs;
         pl.jobs = jobs_dev;
         pl.one = one;
@@ -770,7 +778,7 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         if (e != hipSuccess) return e;
     }
     tr.begin();
-    e = launch_ptrans(p.field, uint64_t(1) << p.lgr[0], L >> p.lgr[0], njobs, jobs_dev, one, s);
+    e = launch_ptrans(p.field, uint64_t(1) << p.lgr[0], L >> p.lgr[0], out_rows, njobs, jobs_dev, one, s);
     tr.end("ptrans");
     if (e != hipSuccess) return e;
     if (any_degen && (e = launch_degen(njobs, jobs_dev, one, s)) != hipSuccess) return e;

@@ -125,6 +125,8 @@ struct PassLaunch {
     int which;            // 0: array A, 1: array B (ignored by C_FUSED, which reads A and B)
     uint64_t S, Mprev;    // strided only
     uint64_t tiles;       // workgroups per job
+    uint64_t out_rows = 0;  // S_INV_PARITY: rows of the level-0 column transform that hold
+                            // needed coefficients (the first out_rows rows; 0 or R: all)
     uint32_t njobs;
     const JobDev *jobs;   // device array of njobs, or nullptr to use `one`
     const JobDev *one;    // host copy for single-job launches (passed by value)
@@ -151,9 +153,10 @@ hipError_t launch_small_batch(const SmallClasses &cls, const JobDev *jobs, uint3
 hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, const JobDev *one, hipStream_t s);
 // Lay out both inputs as L-bit coefficient strings (eb[0], eb[1]).
 hipError_t launch_embed(uint32_t njobs, uint64_t max_L, const JobDev *jobs, const JobDev *one, hipStream_t s);
-// Tile-major parity units of the last inverse pass -> packed natural order (pb).
-hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint32_t njobs, const JobDev *jobs, const JobDev *one,
-                         hipStream_t s);
+// Tile-major parity units of the last inverse pass -> packed natural order (pb),
+// rows [0, rows) of R (the rows that hold needed coefficients).
+hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint64_t rows, uint32_t njobs, const JobDev *jobs,
+                         const JobDev *one, hipStream_t s);
 // Dodis degenerate-input check (writes flags).
 hipError_t launch_degen(uint32_t njobs, const JobDev *jobs, const JobDev *one, hipStream_t s);
 

@@ -426,7 +426,10 @@ struct KArgs {
 // and the table words of its inverse twiddles) before it transforms the
 // current one, so that HBM latency overlaps the arithmetic. The Stockham
 // twiddles of the column transform stay in LDS beside the tile.
-template <class F, int LGR, int MODE>
+// TQ (the last inverse pass only): the last step's outputs t < TQ of each group
+// are the rows that hold needed coefficients (0: all); the arithmetic of the
+// others is dropped at compile time.
+template <class F, int LGR, int MODE, int TQ = 0>
 __global__ void __launch_bounds__((Tile<F, LGR, true, 1, MODE>::NT))
 __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))) k_strided(KArgs a) {
     using Tl = Tile<F, LGR, true, 1, MODE>;
@@ -580,7 +583,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
             const uint64_t rstep = (uint64_t)(R / RL) * a.S;
             uint64_t gi = base + (uint64_t)j * a.S + c;
 #pragma unroll
-            for (int t = 0; t < RL; ++t, gi += rstep) {
+            for (int t = 0; t < (TQ ? TQ : RL); ++t, gi += rstep) {
                 const int r = j + t * (R / RL);
                 T x = v[q * RL + t];
                 if constexpr (FWD) {
@@ -1029,14 +1032,26 @@ static unsigned strided_grid(uint64_t tiles) {
 template <class F, int LGR>
 static hipError_t strided_one(const PassLaunch &p, const KArgs &ka0, hipStream_t s) {
     const KArgs &ka = ka0;
-#define L1(M)                                                                                    \
-    hipLaunchKernelGGL((k_strided<F, LGR, M>), dim3(strided_grid<Tile<F, LGR, true, 1, M>>(p.tiles), p.njobs), \
+#define L1(M, Q)                                                                                 \
+    hipLaunchKernelGGL((k_strided<F, LGR, M, Q>), dim3(strided_grid<Tile<F, LGR, true, 1, M>>(p.tiles), p.njobs), \
                        dim3(Tile<F, LGR, true, 1, M>::NT), 0, s, ka)
+    // last inverse pass: rows j + t R/RL of group j come out of its last step's
+    // output t, so the first out_rows rows need t < ceil(out_rows RL / R)
+    constexpr int RL = Ends<Tile<F, LGR, true, 1, S_INV_PARITY>, true>::RAD_LAST;
+    const uint64_t R = uint64_t(1) << LGR;
+    const uint64_t tq = p.out_rows ? (p.out_rows * RL + R - 1) / R : (uint64_t)RL;
     switch (p.mode) {
-        case S_FWD_BITS: L1(S_FWD_BITS); break;
-        case S_FWD: L1(S_FWD); break;
-        case S_INV: L1(S_INV); break;
-        default: L1(S_INV_PARITY); break;
+        case S_FWD_BITS: L1(S_FWD_BITS, 0); break;
+        case S_FWD: L1(S_FWD, 0); break;
+        case S_INV: L1(S_INV, 0); break;
+        default:
+            if (tq <= RL / 4)
+                L1(S_INV_PARITY, RL / 4);
+            else if (tq <= RL / 2)
+                L1(S_INV_PARITY, RL / 2);
+            else
+                L1(S_INV_PARITY, 0);
+            break;
     }
 #undef L1
     return hipGetLastError();
@@ -1273,13 +1288,14 @@ hipError_t launch_embed(uint32_t njobs, uint64_t max_L, const JobDev *jobs, cons
     return hipGetLastError();
 }
 
-hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint32_t njobs, const JobDev *jobs, const JobDev *one,
-                         hipStream_t s) {
+hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint64_t rows, uint32_t njobs, const JobDev *jobs,
+                         const JobDev *one, hipStream_t s) {
     JobDev o;
     if (one) o = *one;
     else std::memset(&o, 0, sizeof(o));
     const int C = strided_cols(field == FIELD_GL ? 64 : 32, S_INV_PARITY);  // columns of the parity pass
-    dim3 grid((unsigned)((R + 63) / 64), (unsigned)((S / C + 63) / 64), njobs);
+    rows = (rows == 0 || rows > R) ? R : rows;
+    dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((S / C + 63) / 64), njobs);
     if (C == 8)
         hipLaunchKernelGGL(k_ptrans<8>, grid, dim3(256), 0, s, jobs, o, R, S);
     else if (C == 16)
