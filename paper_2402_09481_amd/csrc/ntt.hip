@@ -190,14 +190,22 @@ __host__ __device__ constexpr int step_twiddle_words(int lgr, int order) {
     return f > i ? f : i;
 }
 
+// Strided passes of the 64-bit field's 256- and 512-row columns keep the
+// Stockham twiddles of their column transform in LDS beside the tile (room is
+// left under the LDS limit of two workgroups per CU); elsewhere each step reads
+// them from the global blocks (the 64-bit field one step early). Measured at
+// 512 rows, against the early global loads: forward passes 5% (bits) and 7%
+// (values) faster, with a third fewer registers.
+__host__ __device__ constexpr bool strided_lds_twiddles(int word_bits, int lgr) {
+    return word_bits == 64 && (lgr == 8 || lgr == 9);
+}
 // Whether a strided pass keeps the next tile's loads in flight: the inverse
-// passes of the 64-bit field's 256- and 512-row columns, where the registers
-// allow it without spilling (4 waves per SIMD). Measured at 512 rows: the two
-// inverse passes 4% and 8% faster; the forward passes slower (bits 13%, values
-// 3%), so they, and everything else, run one workgroup per tile with the
-// Stockham twiddles read from the global blocks.
+// passes among those, where the registers allow it without spilling (4 waves
+// per SIMD). Measured at 512 rows: the two inverse passes 4% and 8% faster; the
+// forward passes slower (bits 13%, values 3%), so they, and everything else,
+// run one workgroup per tile.
 __host__ __device__ constexpr bool strided_prefetch(int word_bits, int lgr, int mode) {
-    return word_bits == 64 && (lgr == 8 || lgr == 9) && (mode == S_INV || mode == S_INV_PARITY);
+    return strided_lds_twiddles(word_bits, lgr) && (mode == S_INV || mode == S_INV_PARITY);
 }
 
 template <class F, int LGR, bool STRIDED, int ORDER = 1, int SMODE = S_FWD_BITS>
@@ -224,7 +232,9 @@ struct Tile {
         return 0;
     }
     static constexpr bool PF = STRIDED && strided_prefetch(F::WORD_BITS, LGR, SMODE);
-    static constexpr int STW_WORDS = PF ? step_twiddle_words(LGR, ORDER) : 0;
+    static constexpr bool LT = STRIDED && strided_lds_twiddles(F::WORD_BITS, LGR);
+    static constexpr int STW_WORDS = LT ? step_twiddle_words(LGR, ORDER) : 0;
+    static_assert(!LT || NSTEPS >= 2, "the LDS twiddles are first read after the first step's barrier");
 
     // contiguous tiles pad one word per 16 so that power-of-two strides spread over banks
     static constexpr int RP = STRIDED ? R : R + R / 16;
@@ -463,7 +473,9 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
 
     uint64_t tile = tile_seq(b, W, 0, a.tiles, REMAP);
     if (tile == NO_TILE) return;
-    if constexpr (PF) {
+    // (the first read of the staged twiddles is in step 1, after the barrier that
+    // follows step 0)
+    if constexpr (Tl::LT) {
         for (int s = 1; s < Tl::NSTEPS; ++s) {
             const int rad = Tl::radix(s, INV), ns = Tl::span(s, INV);
             const T *src = (const T *)a.tb.stk + stk_offset(rad, ns, INV);
@@ -545,9 +557,8 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
     issue(tile);
     finish(v);
     if constexpr (PF) {
-        // the first tile's values in registers before the loop (a forward pass takes
-        // them as loaded: without this use the loop would start with a wait for every
-        // memory operation in flight)
+        // the first tile's values in registers before the loop, which otherwise could
+        // start with a wait for every memory operation in flight
 #pragma unroll
         for (int i = 0; i < EPT; ++i) asm volatile("" : "+v"(v[i]));
         __syncthreads();  // the twiddles staged in LDS
@@ -566,7 +577,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
         const uint64_t base = blk * a.Mprev + ct * C;
         // without the LDS copy, the 64-bit field's steps load their twiddles one step
         // early (registers are free up to 128 at 4 waves per SIMD)
-        run_steps_from<F, Tl, INV, 0, (!PF && F::WORD_BITS == 64 && LGR <= 9), PF>(v, lds, a.tb, stw);
+        run_steps_from<F, Tl, INV, 0, (!Tl::LT && F::WORD_BITS == 64 && LGR <= 9), Tl::LT>(v, lds, a.tb, stw);
 #pragma unroll
         for (int q = 0; q < GL; ++q) {
             int c, j;
