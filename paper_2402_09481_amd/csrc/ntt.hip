@@ -176,38 +176,58 @@ __host__ __device__ constexpr int step_span(int lgr, int order, int s, bool inv)
     for (int i = 0; i < s; ++i) ns *= step_radix(lgr, order, i, inv);
     return ns;
 }
-// Stockham twiddles of one direction's steps as the strided kernel keeps them
-// in LDS: the block of step s >= 1 ((radix - 1) span words, laid out as the
-// global block) at step_twiddle_off(s); step 0 has none.
-__host__ __device__ constexpr int step_twiddle_off(int lgr, int order, int s, bool inv) {
+// Stockham twiddles kept in LDS beside a tile. The block of step s ((radix - 1)
+// span words, laid out as the global block; step 0 has none) is local for every
+// step of a strided tile, and for the steps of a contiguous tile whose block
+// has at most CTW_MAX words (the large blocks of its last steps stay global, so
+// that the tile's workgroups per CU do not drop). A strided kernel runs one
+// direction; a contiguous tile holds the forward blocks, then the inverse ones.
+constexpr int CTW_MAX = 512;
+__host__ __device__ constexpr int step_block_words(int lgr, int order, int s, bool inv) {
+    return (step_radix(lgr, order, s, inv) - 1) * step_span(lgr, order, s, inv);
+}
+__host__ __device__ constexpr bool step_twiddle_local(int lgr, int order, bool strided, int s, bool inv) {
+    return s >= 1 && s < (lgr + 3) / 4 && (strided || step_block_words(lgr, order, s, inv) <= CTW_MAX);
+}
+__host__ __device__ constexpr int step_twiddle_dir_words(int lgr, int order, bool strided, bool inv) {
     int o = 0;
-    for (int i = 1; i < s; ++i) o += (step_radix(lgr, order, i, inv) - 1) * step_span(lgr, order, i, inv);
+    for (int i = 1; i < (lgr + 3) / 4; ++i)
+        if (step_twiddle_local(lgr, order, strided, i, inv)) o += step_block_words(lgr, order, i, inv);
     return o;
 }
-__host__ __device__ constexpr int step_twiddle_words(int lgr, int order) {
-    const int nsteps = (lgr + 3) / 4;
-    const int f = step_twiddle_off(lgr, order, nsteps, false), i = step_twiddle_off(lgr, order, nsteps, true);
-    return f > i ? f : i;
+__host__ __device__ constexpr int step_twiddle_off(int lgr, int order, bool strided, int s, bool inv) {
+    int o = (strided || !inv) ? 0 : step_twiddle_dir_words(lgr, order, strided, false);
+    for (int i = 1; i < s; ++i)
+        if (step_twiddle_local(lgr, order, strided, i, inv)) o += step_block_words(lgr, order, i, inv);
+    return o;
+}
+__host__ __device__ constexpr int step_twiddle_words(int lgr, int order, bool strided) {
+    const int f = step_twiddle_dir_words(lgr, order, strided, false);
+    const int i = step_twiddle_dir_words(lgr, order, strided, true);
+    return strided ? (f > i ? f : i) : f + i;
 }
 
-// Strided passes of the 64-bit field's 256- and 512-row columns keep the
-// Stockham twiddles of their column transform in LDS beside the tile (room is
-// left under the LDS limit of two workgroups per CU); elsewhere each step reads
-// them from the global blocks (the 64-bit field one step early). Measured at
-// 512 rows, against the early global loads: forward passes 5% (bits) and 7%
-// (values) faster, with a third fewer registers.
-__host__ __device__ constexpr bool strided_lds_twiddles(int word_bits, int lgr) {
-    return word_bits == 64 && (lgr == 8 || lgr == 9);
+// Where the Stockham twiddles of a column or row transform are read from LDS
+// (the blocks that step_twiddle_local admits) rather than from the global
+// blocks in every step (the 64-bit field one step early): every strided pass;
+// the contiguous passes without the pointwise product and inverse (C_FWD,
+// C_PROD). Measured against the global loads: 64-bit strided forward passes
+// 5% (bits) and 7% (values) faster with a third fewer registers, 32-bit
+// strided passes 8-10% faster, the 64-bit row pass 9% faster; the fused row
+// pass 2% slower, so it keeps the global loads.
+__host__ __device__ constexpr bool lds_twiddles(bool strided, int cmode) {
+    return strided || cmode == C_FWD || cmode == C_PROD;
 }
 // Whether a strided pass keeps the next tile's loads in flight: the inverse
-// passes among those, where the registers allow it without spilling (4 waves
-// per SIMD). Measured at 512 rows: the two inverse passes 4% and 8% faster; the
+// passes of the 64-bit field's 256- and 512-row columns, where the registers
+// allow it without spilling (4 waves per SIMD). Measured at 512 rows: the two inverse passes 4% and 8% faster; the
 // forward passes slower (bits 13%, values 3%), so they, and everything else,
 // run one workgroup per tile.
 __host__ __device__ constexpr bool strided_prefetch(int word_bits, int lgr, int mode) {
-    return strided_lds_twiddles(word_bits, lgr) && (mode == S_INV || mode == S_INV_PARITY);
+    return word_bits == 64 && (lgr == 8 || lgr == 9) && (mode == S_INV || mode == S_INV_PARITY);
 }
 
+// SMODE: the pass mode (StridedMode for strided tiles, ContigMode otherwise).
 template <class F, int LGR, bool STRIDED, int ORDER = 1, int SMODE = S_FWD_BITS>
 struct Tile {
     using T = typename F::T;
@@ -224,21 +244,33 @@ struct Tile {
 
     __host__ __device__ static constexpr int radix(int s, bool inv) { return step_radix(LGR, ORDER, s, inv); }
     __host__ __device__ static constexpr int span(int s, bool inv) { return step_span(LGR, ORDER, s, inv); }
-    __host__ __device__ static constexpr int stw_off(int s, bool inv) { return step_twiddle_off(LGR, ORDER, s, inv); }
-    // LDS offset of the twiddle block of the step with radix rad and span ns
+    __host__ __device__ static constexpr bool stw_local(int s, bool inv) {
+        return step_twiddle_local(LGR, ORDER, STRIDED, s, inv);
+    }
+    __host__ __device__ static constexpr int stw_off(int s, bool inv) {
+        return step_twiddle_off(LGR, ORDER, STRIDED, s, inv);
+    }
+    // the step with radix rad and span ns: whether its block is in LDS, and where
+    __host__ __device__ static constexpr bool stw_has(int rad, int ns, bool inv) {
+        for (int i = 1; i < NSTEPS; ++i)
+            if (radix(i, inv) == rad && span(i, inv) == ns) return stw_local(i, inv);
+        return false;
+    }
     __host__ __device__ static constexpr int stw_block(int rad, int ns, bool inv) {
         for (int i = 1; i < NSTEPS; ++i)
             if (radix(i, inv) == rad && span(i, inv) == ns) return stw_off(i, inv);
         return 0;
     }
     static constexpr bool PF = STRIDED && strided_prefetch(F::WORD_BITS, LGR, SMODE);
-    static constexpr bool LT = STRIDED && strided_lds_twiddles(F::WORD_BITS, LGR);
-    static constexpr int STW_WORDS = LT ? step_twiddle_words(LGR, ORDER) : 0;
+    static constexpr bool LT = lds_twiddles(STRIDED, SMODE);
+    // (a contiguous tile with LDS twiddles runs the forward direction only)
+    static constexpr int STW_WORDS =
+        !LT ? 0 : STRIDED ? step_twiddle_words(LGR, ORDER, true) : step_twiddle_dir_words(LGR, ORDER, false, false);
     static_assert(!LT || NSTEPS >= 2, "the LDS twiddles are first read after the first step's barrier");
 
     // contiguous tiles pad one word per 16 so that power-of-two strides spread over banks
     static constexpr int RP = STRIDED ? R : R + R / 16;
-    static constexpr int LDS_WORDS = STRIDED ? C * R + STW_WORDS : C * RP;
+    static constexpr int LDS_WORDS = (STRIDED ? C * R : C * RP) + STW_WORDS;
     // Waves per SIMD that strided kernels promise the register allocator: as
     // many as the LDS admits (160 KiB per CU, 4 SIMDs), at most 8. A register
     // count above that would leave LDS idle and halve the resident workgroups
@@ -267,11 +299,10 @@ template <class F, class Tl, int RAD, int NS, bool INV, bool LT = false>
 __device__ inline void step_compute(typename F::T *v, const Tables &tb, const typename F::T *stw = nullptr) {
     using T = typename F::T;
     static_assert(NS * RAD <= (1 << TWIN_LG) && RAD <= 16, "step beyond the Stockham twiddle blocks");
-    const T *tw;
-    if constexpr (LT)
-        tw = stw + Tl::stw_block(RAD, NS, INV);
-    else
-        tw = (const T *)tb.stk + stk_offset(RAD, NS, INV);
+    const T *tw = (const T *)tb.stk + stk_offset(RAD, NS, INV);
+    if constexpr (LT) {
+        if constexpr (Tl::stw_has(RAD, NS, INV)) tw = stw + Tl::stw_block(RAD, NS, INV);
+    }
     constexpr int GPT = Tl::EPT / RAD;
 #pragma unroll
     for (int q = 0; q < GPT; ++q) {
@@ -624,10 +655,24 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
 
 template <class F, int LGR, int MODE>
 __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
-    using Tl = Tile<F, LGR, false, (MODE == C_FWD ? 1 : 2)>;
+    using Tl = Tile<F, LGR, false, (MODE == C_FWD ? 1 : 2), MODE>;
     using T = typename F::T;
     constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
-    __shared__ T lds[Tl::LDS_WORDS];
+    constexpr bool FUSED = (MODE == C_FUSED || MODE == C_FUSED2);
+    __shared__ T lds[C * Tl::RP];
+    __shared__ T stw[Tl::STW_WORDS > 0 ? Tl::STW_WORDS : 1];
+    // the small Stockham twiddle blocks of the forward transform, first read in
+    // step 1, after the barrier that follows step 0
+    if constexpr (Tl::LT) {
+        static_assert(!FUSED, "LDS twiddles hold the forward blocks only");
+#pragma unroll
+        for (int s = 1; s < Tl::NSTEPS; ++s) {
+            if (!Tl::stw_local(s, false)) continue;
+            const int rad = Tl::radix(s, false), ns = Tl::span(s, false);
+            const T *src = (const T *)a.tb.stk + stk_offset(rad, ns, false);
+            for (int i = threadIdx.x; i < (rad - 1) * ns; i += Tl::NT) stw[Tl::stw_off(s, false) + i] = gload(src + i);
+        }
+    }
 
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
     T *data = (T *)(a.which ? J.B : J.A);
@@ -660,7 +705,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             for (int t = 0; t < RADL; ++t) sv[q * RADL + t] = gload(spec + base + (uint64_t)c * R + j + t * (R / RADL));
         }
     }
-    run_steps_from<F, Tl, false, 0>(v, lds, a.tb);
+    run_steps_from<F, Tl, false, 0, false, Tl::LT>(v, lds, a.tb, stw);
     if constexpr (MODE == C_FUSED || MODE == C_FUSED2) {
         static_assert(Ends<Tl, true>::RAD_FIRST == RADL, "register hand-over needs equal radices");
         // (the constant K is applied by the last inverse pass)
@@ -678,7 +723,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             }
         }
         __syncthreads();  // LDS is reused by the inverse steps
-        run_steps_from<F, Tl, true, 0>(v, lds, a.tb);
+        run_steps_from<F, Tl, true, 0, false, Tl::LT>(v, lds, a.tb, stw);
         constexpr int RADI = Ends<Tl, true>::RAD_LAST;
 #pragma unroll
         for (int q = 0; q < EPT / RADI; ++q) {
