@@ -209,24 +209,15 @@ __host__ __device__ constexpr int step_twiddle_words(int lgr, int order, bool st
 
 // Where the Stockham twiddles of a column or row transform are read from LDS
 // (the blocks that step_twiddle_local admits) rather than from the global
-// blocks in every step (the 64-bit field one step early): every strided pass;
-// the contiguous passes without the pointwise product and inverse (C_FWD,
-// C_PROD). Measured against the global loads: 64-bit strided forward passes
-// 5% (bits) and 7% (values) faster with a third fewer registers, 32-bit
-// strided passes 8-10% faster, the 64-bit row pass 9% faster; the fused row
-// pass 2% slower, so it keeps the global loads.
+// blocks in every step: every strided pass; the contiguous passes without the
+// pointwise product and inverse (C_FWD, C_PROD). Measured against global loads
+// (the 64-bit field's issued one step early): 64-bit strided passes 5-9%
+// faster with half the registers, 32-bit strided passes 8-10% faster, the
+// 64-bit row pass 9% faster; the fused row pass 2% slower, so it keeps the
+// global loads.
 __host__ __device__ constexpr bool lds_twiddles(bool strided, int cmode) {
     return strided || cmode == C_FWD || cmode == C_PROD;
 }
-// Whether a strided pass keeps the next tile's loads in flight: the inverse
-// passes of the 64-bit field's 256- and 512-row columns, where the registers
-// allow it without spilling (4 waves per SIMD). Measured at 512 rows: the two inverse passes 4% and 8% faster; the
-// forward passes slower (bits 13%, values 3%), so they, and everything else,
-// run one workgroup per tile.
-__host__ __device__ constexpr bool strided_prefetch(int word_bits, int lgr, int mode) {
-    return word_bits == 64 && (lgr == 8 || lgr == 9) && (mode == S_INV || mode == S_INV_PARITY);
-}
-
 // SMODE: the pass mode (StridedMode for strided tiles, ContigMode otherwise).
 template <class F, int LGR, bool STRIDED, int ORDER = 1, int SMODE = S_FWD_BITS>
 struct Tile {
@@ -261,7 +252,6 @@ struct Tile {
             if (radix(i, inv) == rad && span(i, inv) == ns) return stw_off(i, inv);
         return 0;
     }
-    static constexpr bool PF = STRIDED && strided_prefetch(F::WORD_BITS, LGR, SMODE);
     static constexpr bool LT = lds_twiddles(STRIDED, SMODE);
     // (a contiguous tile with LDS twiddles runs the forward direction only)
     static constexpr int STW_WORDS =
@@ -344,73 +334,13 @@ __device__ inline void step_store_lds(const typename F::T *v, typename F::T *lds
     }
 }
 
-// Stockham twiddles of one step, tw[q RAD + t] = w_(NS RAD)^(+-t jm) for t >= 1
-// (the values step_compute reads), loaded ahead of the step that uses them.
-template <class F, class Tl, int RAD, int NS, bool INV>
-__device__ inline void step_twiddles(typename F::T *tw, const Tables &tb) {
-    using T = typename F::T;
-    static_assert(NS * RAD <= (1 << TWIN_LG) && RAD <= 16, "step beyond the Stockham twiddle blocks");
-    const T *src = (const T *)tb.stk + stk_offset(RAD, NS, INV);
-    constexpr int GPT = Tl::EPT / RAD;
-#pragma unroll
-    for (int q = 0; q < GPT; ++q) {
-        int c, j;
-        Tl::template coords<RAD>(q, c, j);
-        (void)c;
-        const int jm = j & (NS - 1);
-#pragma unroll
-        for (int t = 1; t < RAD; ++t) tw[q * RAD + t] = src[(t - 1) * NS + jm];
-    }
-}
-
-template <class F, class Tl, int RAD>
-__device__ inline void step_compute_pre(typename F::T *v, const typename F::T *tw, int Ns, bool inv) {
-    constexpr int GPT = Tl::EPT / RAD;
-#pragma unroll
-    for (int q = 0; q < GPT; ++q) {
-        if (Ns > 1) {
-#pragma unroll
-            for (int t = 1; t < RAD; ++t) v[q * RAD + t] = F::mul_tw(v[q * RAD + t], tw[q * RAD + t]);
-        }
-        dft_reg<F, RAD>(&v[q * RAD], inv);
-    }
-}
-
-// As run_steps_from, with each step's twiddle loads issued one step early (before
-// the LDS exchange that precedes their use), so that their latency overlaps the
-// previous step's arithmetic. Used by the strided tiles of the 64-bit field,
-// which LDS holds to 4 waves per SIMD, so that the prefetch's registers are free.
-template <class F, class Tl, bool INV, int S>
-__device__ inline void run_steps_pre(typename F::T *v, typename F::T *lds, const Tables &tb,
-                                     const typename F::T *tw) {
-    using T = typename F::T;
-    if constexpr (S < Tl::NSTEPS) {
-        constexpr int RAD = Tl::radix(S, INV);
-        constexpr int NS = Tl::span(S, INV);
-        if constexpr (S > 0) step_load_lds<F, Tl, RAD>(v, lds);
-        T twn[Tl::EPT];
-        if constexpr (S + 1 < Tl::NSTEPS)
-            step_twiddles<F, Tl, Tl::radix(S + 1, INV), Tl::span(S + 1, INV), INV>(twn, tb);
-        step_compute_pre<F, Tl, RAD>(v, tw, NS, INV);
-        if constexpr (S + 1 < Tl::NSTEPS) {
-            __syncthreads();
-            step_store_lds<F, Tl, RAD>(v, lds, NS);
-            __syncthreads();
-            run_steps_pre<F, Tl, INV, S + 1>(v, lds, tb, twn);
-        }
-    }
-}
-
 // Run steps [s0, s1) of a transform whose inputs for step s0 are already in
 // registers; the outputs of step s1-1 stay in registers (positions of the
 // last-step layout if s1 == NSTEPS). LDS exchanges in between.
-template <class F, class Tl, bool INV, int S, bool PRE = false, bool LT = false>
+template <class F, class Tl, bool INV, int S, bool LT = false>
 __device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, const Tables &tb,
                                       const typename F::T *stw = nullptr) {
-    if constexpr (S == 0 && PRE) {
-        typename F::T tw0[Tl::EPT];  // the first step has no twiddles
-        run_steps_pre<F, Tl, INV, 0>(v, lds, tb, tw0);
-    } else if constexpr (S < Tl::NSTEPS) {
+    if constexpr (S < Tl::NSTEPS) {
         constexpr int RAD = Tl::radix(S, INV);
         constexpr int NS = Tl::span(S, INV);
         if constexpr (S > 0) {
@@ -422,7 +352,7 @@ __device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, cons
             __syncthreads();  // every read of the previous layout is done
             step_store_lds<F, Tl, RAD>(v, lds, NS);
             __syncthreads();
-            run_steps_from<F, Tl, INV, S + 1, false, LT>(v, lds, tb, stw);
+            run_steps_from<F, Tl, INV, S + 1, LT>(v, lds, tb, stw);
         }
     }
 }
@@ -436,21 +366,14 @@ struct Ends {
 // ------------------------------------------------------------------ strided pass
 
 // Workgroups are dealt to the 8 XCDs (each with its own L2 and address
-// translation cache) round-robin by index. The k-th tile of workgroup b of a
-// grid of W (tiles b, b + W, ... in order, ~0 past the n tiles) is, for the
-// value passes (remap), chosen so that every XCD runs through one contiguous
-// run of n/8 tiles, so neighbouring column groups (the same rows, the same
-// memory pages) are read through the same L2. The remap needs W and n to be
-// multiples of 8; otherwise, and for the other passes, tile b + k W.
-constexpr uint64_t NO_TILE = ~uint64_t(0);
-__device__ inline uint64_t tile_seq(uint64_t b, uint64_t W, uint64_t k, uint64_t n, bool remap) {
+// translation cache) round-robin by index. Tile = this remap of the index gives
+// every XCD one contiguous run of tiles, so neighbouring column groups (the same
+// rows, the same memory pages) are read through the same L2. A bijection when
+// the grid is a multiple of 8, the identity otherwise.
+__device__ inline uint64_t xcd_tile(uint64_t b, uint64_t nb) {
     constexpr uint64_t XCDS = 8;
-    if (remap && W % XCDS == 0 && n % XCDS == 0) {
-        const uint64_t i = b / XCDS + k * (W / XCDS), chunk = n / XCDS;
-        return i < chunk ? (b % XCDS) * chunk + i : NO_TILE;
-    }
-    const uint64_t t = b + k * W;
-    return t < n ? t : NO_TILE;
+    if (nb % XCDS) return b;
+    return (b % XCDS) * (nb / XCDS) + b / XCDS;
 }
 
 struct KArgs {
@@ -458,15 +381,11 @@ struct KArgs {
     JobDev one;
     Tables tb;
     uint64_t S, Mprev;
-    uint64_t tiles;  // tiles per job
-    int which;       // array read and written (0: A, 1: B)
+    int which;  // array read and written (0: A, 1: B)
 };
 
-// A strided pass. With prefetch it is persistent: each workgroup runs through
-// its tiles in order and issues the next tile's loads (values, or bit units,
-// and the table words of its inverse twiddles) before it transforms the
-// current one, so that HBM latency overlaps the arithmetic. The Stockham
-// twiddles of the column transform stay in LDS beside the tile.
+// A strided pass: one workgroup per tile of C adjacent columns of R rows. The
+// Stockham twiddles of the column transform are staged in LDS beside the tile.
 // TQ (the last inverse pass only): the last step's outputs t < TQ of each group
 // are the rows that hold needed coefficients (0: all); the arithmetic of the
 // others is dropped at compile time.
@@ -481,173 +400,109 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
     constexpr bool BITS = MODE == S_FWD_BITS;
     constexpr int RF = Ends<Tl, INV>::RAD_FIRST, GF = EPT / RF;
     constexpr int RL = Ends<Tl, INV>::RAD_LAST, GL = EPT / RL;
-    constexpr bool PF = Tl::PF;
+    static_assert(Tl::LT, "strided tiles keep their twiddles in LDS");
     using Unit = UnitOf<C>;
-    using X = typename std::conditional<BITS, uint32_t, T>::type;
     __shared__ T lds[C * R];
     __shared__ T stw[Tl::STW_WORDS > 0 ? Tl::STW_WORDS : 1];
 
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
     T *data = (T *)(a.which ? J.B : J.A);
-    const Unit *ub = (const Unit *)J.eb[a.which];
-    // (the descriptor is read once: the tile stores could alias it)
-    Unit *const par = (Unit *)J.eb[0];
-    const T Kc = (T)J.K;
     const T *thi = (const T *)a.tb.hi, *tlo = (const T *)a.tb.lo;
     const uint64_t colTiles = a.S / C;
-    const int shift = F::LGMAX - (63 - __builtin_clzll(a.Mprev));  // 2^LGMAX / Mprev = 2^shift
-    const uint64_t emask = (uint64_t(1) << F::LGMAX) - 1;
     // (measured: the remap helps the value passes and slows the bit-reading first
     // forward pass)
-    constexpr bool REMAP = (MODE == S_FWD || MODE == S_INV);
-    const uint64_t W = gridDim.x, b = blockIdx.x;
+    const uint64_t tile = (MODE == S_FWD || MODE == S_INV) ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint64_t blk = tile / colTiles, ct = tile - blk * colTiles;
+    const uint64_t base = blk * a.Mprev + ct * C;
+    const int shift = F::LGMAX - (63 - __builtin_clzll(a.Mprev));  // 2^LGMAX / Mprev = 2^shift
+    const uint64_t emask = (uint64_t(1) << F::LGMAX) - 1;
 
-    uint64_t tile = tile_seq(b, W, 0, a.tiles, REMAP);
-    if (tile == NO_TILE) return;
-    // (the first read of the staged twiddles is in step 1, after the barrier that
-    // follows step 0)
-    if constexpr (Tl::LT) {
-        for (int s = 1; s < Tl::NSTEPS; ++s) {
-            const int rad = Tl::radix(s, INV), ns = Tl::span(s, INV);
-            const T *src = (const T *)a.tb.stk + stk_offset(rad, ns, INV);
-            for (int i = threadIdx.x; i < (rad - 1) * ns; i += NT) stw[Tl::stw_off(s, INV) + i] = gload(src + i);
-        }
+    // the twiddle blocks of steps 1.., first read in step 1, after the barrier
+    // that follows step 0
+    for (int s = 1; s < Tl::NSTEPS; ++s) {
+        const int rad = Tl::radix(s, INV), ns = Tl::span(s, INV);
+        const T *src = (const T *)a.tb.stk + stk_offset(rad, ns, INV);
+        for (int i = threadIdx.x; i < (rad - 1) * ns; i += NT) stw[Tl::stw_off(s, INV) + i] = gload(src + i);
     }
-
-    // loads of a tile in the first step's layout: group q of thread (c, j) holds
-    // rows j + t R/RF of column c; the inverse twiddle w^-(col r) of those rows is
-    // a geometric sequence in t, from two table twiddles (four table words)
-    X xr[EPT];
-    T tr[INV ? 4 * GF : 1];
-    auto issue = [&](uint64_t tl) {
-        const uint64_t blk = tl / colTiles, ct = tl - blk * colTiles;
-        const uint64_t base = blk * a.Mprev + ct * C;
-#pragma unroll
-        for (int q = 0; q < GF; ++q) {
-            int c, j;
-            Tl::template coords<RF>(q, c, j);
-            if constexpr (INV) {
-                const uint64_t col = ct * C + c;
-                const uint64_t ew = (uint64_t(0) - ((col * (uint64_t)j) << shift)) & emask;
-                const uint64_t es = (uint64_t(0) - ((col * (uint64_t)(R / RF)) << shift)) & emask;
-                tr[4 * q] = gload(thi + (ew >> 16));
-                tr[4 * q + 1] = gload(tlo + (ew & 0xFFFF));
-                tr[4 * q + 2] = gload(thi + (es >> 16));
-                tr[4 * q + 3] = gload(tlo + (es & 0xFFFF));
-            }
-            // element index of row r = j + t R/RF, column c: a running sum (one
-            // 64-bit add per element instead of a 32x64-bit product)
-            const uint64_t rstep = (uint64_t)(R / RF) * a.S;
-            uint64_t gi = base + (uint64_t)j * a.S + c;
-#pragma unroll
-            for (int t = 0; t < RF; ++t, gi += rstep) {
-                // bits: a row segment of the tile is C adjacent bits starting at a
-                // multiple of C, one C-bit unit, the same address for every lane
-                // of the row
-                if constexpr (BITS)
-                    xr[q * RF + t] = gload(ub + (gi - c) / C);
-                else
-                    xr[q * RF + t] = gload(data + gi);
-            }
-        }
-    };
-
-    // the issued loads of a tile as the first step's values (inverse: times their
-    // twiddles)
-    auto finish = [&](T *v) {
-#pragma unroll
-        for (int q = 0; q < GF; ++q) {
-            int c, j;
-            Tl::template coords<RF>(q, c, j);
-            T wt = T(), st = T();
-            if constexpr (INV) {
-                wt = F::tw_combine(tr[4 * q], tr[4 * q + 1]);
-                st = F::tw_combine(tr[4 * q + 2], tr[4 * q + 3]);
-                // the last inverse pass also applies the pointwise constant K (L^-1
-                // and Montgomery factors): one product per group at the start of
-                // its twiddle sequence instead of one per value in the fused pass
-                if constexpr (MODE == S_INV_PARITY) wt = F::tw_combine(wt, Kc);
-            }
-#pragma unroll
-            for (int t = 0; t < RF; ++t) {
-                T x;
-                if constexpr (BITS)
-                    x = F::from_bit((xr[q * RF + t] >> c) & 1u);
-                else
-                    x = xr[q * RF + t];
-                if constexpr (INV) {
-                    x = F::mul_tw(x, wt);
-                    if (t + 1 < RF) wt = F::tw_combine(wt, st);
-                }
-                v[q * RF + t] = x;
-            }
-        }
-    };
 
     T v[EPT];
-    issue(tile);
-    finish(v);
-    if constexpr (PF) {
-        // the first tile's values in registers before the loop, which otherwise could
-        // start with a wait for every memory operation in flight
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) asm volatile("" : "+v"(v[i]));
-        __syncthreads();  // the twiddles staged in LDS
+    for (int q = 0; q < GF; ++q) {
+        int c, j;
+        Tl::template coords<RF>(q, c, j);
+        // inverse: twiddle w^-(col r) for rows r = j + t R/RF, a geometric
+        // sequence in t: two table twiddles per group, then products
+        T wt = T(), st = T();
+        if constexpr (INV) {
+            const uint64_t col = ct * C + c;
+            const uint64_t ew = (uint64_t(0) - ((col * (uint64_t)j) << shift)) & emask;
+            const uint64_t es = (uint64_t(0) - ((col * (uint64_t)(R / RF)) << shift)) & emask;
+            wt = F::tw_combine(gload(thi + (ew >> 16)), gload(tlo + (ew & 0xFFFF)));
+            st = F::tw_combine(gload(thi + (es >> 16)), gload(tlo + (es & 0xFFFF)));
+            // the last inverse pass also applies the pointwise constant K (L^-1
+            // and Montgomery factors): one product per group at the start of
+            // its twiddle sequence instead of one per value in the fused pass
+            if constexpr (MODE == S_INV_PARITY) wt = F::tw_combine(wt, (T)J.K);
+        }
+        // element index of row r = j + t R/RF, column c: a running sum (one
+        // 64-bit add per element instead of a 32x64-bit product)
+        const uint64_t rstep = (uint64_t)(R / RF) * a.S;
+        uint64_t gi = base + (uint64_t)j * a.S + c;
+#pragma unroll
+        for (int t = 0; t < RF; ++t, gi += rstep) {
+            T x;
+            if constexpr (BITS) {
+                // a row segment of the tile is C adjacent bits starting at a
+                // multiple of C: one C-bit unit, the same address for every
+                // lane of the row
+                const Unit *ub = (const Unit *)J.eb[a.which];
+                x = F::from_bit((uint32_t)(gload(ub + (gi - c) / C) >> c) & 1u);
+            } else {
+                x = gload(data + gi);
+            }
+            if constexpr (INV) {
+                x = F::mul_tw(x, wt);
+                if (t + 1 < RF) wt = F::tw_combine(wt, st);
+            }
+            v[q * RF + t] = x;
+        }
     }
-    // Each round: (prefetch) the next tile's loads, this tile's column transform
-    // and stores, then the next tile's values from its loads. The values are
-    // taken at the end of the round, so the loop never starts by waiting for
-    // memory operations that are still in flight.
-    for (uint64_t k = 1;; ++k) {
-        const uint64_t next = PF ? tile_seq(b, W, k, a.tiles, REMAP) : NO_TILE;
-        if constexpr (PF) {
-            if (next != NO_TILE) issue(next);
-        }
-
-        const uint64_t blk = tile / colTiles, ct = tile - blk * colTiles;
-        const uint64_t base = blk * a.Mprev + ct * C;
-        // without the LDS copy, the 64-bit field's steps load their twiddles one step
-        // early (registers are free up to 128 at 4 waves per SIMD)
-        run_steps_from<F, Tl, INV, 0, (!Tl::LT && F::WORD_BITS == 64 && LGR <= 9), Tl::LT>(v, lds, a.tb, stw);
+    run_steps_from<F, Tl, INV, 0, true>(v, lds, a.tb, stw);
 #pragma unroll
-        for (int q = 0; q < GL; ++q) {
-            int c, j;
-            Tl::template coords<RL>(q, c, j);
-            // forward: twiddle w^(col r), the same geometric sequence in t
-            T wt = T(), st = T();
+    for (int q = 0; q < GL; ++q) {
+        int c, j;
+        Tl::template coords<RL>(q, c, j);
+        // forward: twiddle w^(col r), the same geometric sequence in t
+        T wt = T(), st = T();
+        if constexpr (FWD) {
+            const uint64_t col = ct * C + c;
+            const uint64_t ew = ((col * (uint64_t)j) << shift) & emask;
+            const uint64_t es = ((col * (uint64_t)(R / RL)) << shift) & emask;
+            wt = F::tw_combine(gload(thi + (ew >> 16)), gload(tlo + (ew & 0xFFFF)));
+            st = F::tw_combine(gload(thi + (es >> 16)), gload(tlo + (es & 0xFFFF)));
+        }
+        const uint64_t rstep = (uint64_t)(R / RL) * a.S;
+        uint64_t gi = base + (uint64_t)j * a.S + c;
+#pragma unroll
+        for (int t = 0; t < (TQ ? TQ : RL); ++t, gi += rstep) {
+            const int r = j + t * (R / RL);
+            T x = v[q * RL + t];
             if constexpr (FWD) {
-                const uint64_t col = ct * C + c;
-                const uint64_t ew = ((col * (uint64_t)j) << shift) & emask;
-                const uint64_t es = ((col * (uint64_t)(R / RL)) << shift) & emask;
-                wt = F::tw_combine(gload(thi + (ew >> 16)), gload(tlo + (ew & 0xFFFF)));
-                st = F::tw_combine(gload(thi + (es >> 16)), gload(tlo + (es & 0xFFFF)));
-            }
-            const uint64_t rstep = (uint64_t)(R / RL) * a.S;
-            uint64_t gi = base + (uint64_t)j * a.S + c;
-#pragma unroll
-            for (int t = 0; t < (TQ ? TQ : RL); ++t, gi += rstep) {
-                const int r = j + t * (R / RL);
-                T x = v[q * RL + t];
-                if constexpr (FWD) {
-                    gstore(data + gi, F::mul_tw(x, wt));
-                    if (t + 1 < RL) wt = F::tw_combine(wt, st);
-                } else if constexpr (MODE == S_INV) {
-                    gstore(data + gi, x);
-                } else {
-                    // level 0 of the inverse: gi is the coefficient index; the C lanes
-                    // of a row hold C consecutive coefficients. Their parities go out
-                    // tile-major (unit (ct, r) at ct*R + r, contiguous per workgroup);
-                    // a transpose kernel turns that into packed natural order.
-                    uint32_t bit = (uint32_t)(F::canon(x) & 1u);
-                    uint64_t mask = __ballot(bit);
-                    const int lane = (int)(threadIdx.x & 63);
-                    if (c == 0) gstore(par + ct * R + r, (Unit)(mask >> (lane & ~(C - 1))));
-                }
+                gstore(data + gi, F::mul_tw(x, wt));
+                if (t + 1 < RL) wt = F::tw_combine(wt, st);
+            } else if constexpr (MODE == S_INV) {
+                gstore(data + gi, x);
+            } else {
+                // level 0 of the inverse: gi is the coefficient index; the C lanes
+                // of a row hold C consecutive coefficients. Their parities go out
+                // tile-major (unit (ct, r) at ct*R + r, contiguous per workgroup);
+                // a transpose kernel turns that into packed natural order.
+                uint32_t bit = (uint32_t)(F::canon(x) & 1u);
+                uint64_t mask = __ballot(bit);
+                const int lane = (int)(threadIdx.x & 63);
+                if (c == 0) gstore((Unit *)J.eb[0] + ct * R + r, (Unit)(mask >> (lane & ~(C - 1))));
             }
         }
-        if (next == NO_TILE) break;
-        finish(v);
-        tile = next;
     }
 }
 
@@ -705,7 +560,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             for (int t = 0; t < RADL; ++t) sv[q * RADL + t] = gload(spec + base + (uint64_t)c * R + j + t * (R / RADL));
         }
     }
-    run_steps_from<F, Tl, false, 0, false, Tl::LT>(v, lds, a.tb, stw);
+    run_steps_from<F, Tl, false, 0, Tl::LT>(v, lds, a.tb, stw);
     if constexpr (MODE == C_FUSED || MODE == C_FUSED2) {
         static_assert(Ends<Tl, true>::RAD_FIRST == RADL, "register hand-over needs equal radices");
         // (the constant K is applied by the last inverse pass)
@@ -723,7 +578,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             }
         }
         __syncthreads();  // LDS is reused by the inverse steps
-        run_steps_from<F, Tl, true, 0, false, Tl::LT>(v, lds, a.tb, stw);
+        run_steps_from<F, Tl, true, 0, Tl::LT>(v, lds, a.tb, stw);
         constexpr int RADI = Ends<Tl, true>::RAD_LAST;
 #pragma unroll
         for (int q = 0; q < EPT / RADI; ++q) {
@@ -1070,26 +925,14 @@ static KArgs make_args(const PassLaunch &p, const Tables &t) {
     ka.S = p.S;
     ka.Mprev = p.Mprev;
     ka.which = p.which;
-    ka.tiles = p.tiles;
     return ka;
-}
-
-// Workgroups of a strided pass per job: with prefetch, as many as the CUs hold
-// at once (256 CUs, the workgroups per CU that LDS admits; a multiple of 8), at
-// most one per tile; without, one per tile.
-constexpr uint64_t DEVICE_CUS = 256;
-template <class Tl>
-static unsigned strided_grid(uint64_t tiles) {
-    if (!Tl::PF) return (unsigned)tiles;
-    const uint64_t w = DEVICE_CUS * (uint64_t)(Tl::WG_BY_LDS > 0 ? Tl::WG_BY_LDS : 1);
-    return (unsigned)(tiles <= w ? tiles : w);
 }
 
 template <class F, int LGR>
 static hipError_t strided_one(const PassLaunch &p, const KArgs &ka0, hipStream_t s) {
     const KArgs &ka = ka0;
 #define L1(M, Q)                                                                                 \
-    hipLaunchKernelGGL((k_strided<F, LGR, M, Q>), dim3(strided_grid<Tile<F, LGR, true, 1, M>>(p.tiles), p.njobs), \
+    hipLaunchKernelGGL((k_strided<F, LGR, M, Q>), dim3((unsigned)p.tiles, p.njobs), \
                        dim3(Tile<F, LGR, true, 1, M>::NT), 0, s, ka)
     // last inverse pass: rows j + t R/RL of group j come out of its last step's
     // output t, so the first out_rows rows need t < ceil(out_rows RL / R)
