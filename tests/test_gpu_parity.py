@@ -109,6 +109,16 @@ def test_toeplitz_multipass_32bit(ctx, n, m):
     run_case(ctx, "toeplitz", n, m, "paper", seed=7 * n + m, px=0.4)
 
 
+@pytest.mark.parametrize("field", ["default", "gl"])
+@pytest.mark.parametrize("n,m", [(65536, 8192), (65536, 32768), (65536, 32769), (65537, 65536)])
+def test_last_pass_row_bounds(ctx, ctx_gl, field, n, m):
+    """The last inverse pass computes only the rows of its column transform that
+    hold output coefficients (the first ceil(m/S) of R rows: a quarter, a half or
+    all of its last step's outputs). Transform 2^17 here, with m = L/16, exactly
+    L/4, one past L/4 and L/2: on and across those bounds, on both fields."""
+    run_case(ctx if field == "default" else ctx_gl, "toeplitz", n, m, "paper", seed=19 * n + m, px=0.4)
+
+
 @pytest.mark.parametrize("n,m", [(11, 5), (13, 13), (61, 60), (1019, 500), (4099, 4099), (8219, 8000),
                                  (16421, 9000), (65587, 32768)])
 def test_dodis(ctx, n, m):
