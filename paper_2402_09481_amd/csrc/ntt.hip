@@ -401,9 +401,14 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
     constexpr int RF = Ends<Tl, INV>::RAD_FIRST, GF = EPT / RF;
     constexpr int RL = Ends<Tl, INV>::RAD_LAST, GL = EPT / RL;
     static_assert(Tl::LT, "strided tiles keep their twiddles in LDS");
+    // The bit-reading pass with a radix-16 first step: that step's first two
+    // butterfly layers are 4-point DFTs of four input bits (inputs t, t+4, t+8,
+    // t+12), read from a 16 x 4 table built here by the same arithmetic.
+    constexpr bool LUT = BITS && RF == 16;
     using Unit = UnitOf<C>;
     __shared__ T lds[C * R];
     __shared__ T stw[Tl::STW_WORDS > 0 ? Tl::STW_WORDS : 1];
+    __shared__ T lut[LUT ? 64 : 1];
 
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
     T *data = (T *)(a.which ? J.B : J.A);
@@ -425,7 +430,25 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
         for (int i = threadIdx.x; i < (rad - 1) * ns; i += NT) stw[Tl::stw_off(s, INV) + i] = gload(src + i);
     }
 
+    if constexpr (LUT) {
+        // entry (idx, k): output k of the first two layers when input 4 i is bit i
+        // of idx and the other inputs are zero (every group of four takes the same
+        // table)
+        if (threadIdx.x < 64) {
+            T u[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) u[i] = F::from_bit(0u);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) u[bitrev<16>(4 * i)] = F::from_bit((threadIdx.x >> (2 + i)) & 1u);
+            dft_layer_k<F, 16, 2, 0>(u);
+            dft_layer_k<F, 16, 4, 0>(u);
+            const int k = threadIdx.x & 3;
+            lut[threadIdx.x] = k == 0 ? u[0] : k == 1 ? u[1] : k == 2 ? u[2] : u[3];
+        }
+    }
+
     T v[EPT];
+    uint32_t bt[LUT ? EPT : 1];  // the input bits of the table path
 #pragma unroll
     for (int q = 0; q < GF; ++q) {
         int c, j;
@@ -456,7 +479,9 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
                 // multiple of C: one C-bit unit, the same address for every
                 // lane of the row
                 const Unit *ub = (const Unit *)J.eb[a.which];
-                x = F::from_bit((uint32_t)(gload(ub + (gi - c) / C) >> c) & 1u);
+                const uint32_t bit = (uint32_t)(gload(ub + (gi - c) / C) >> c) & 1u;
+                if constexpr (LUT) bt[q * RF + t] = bit;
+                x = F::from_bit(bit);
             } else {
                 x = gload(data + gi);
             }
@@ -467,7 +492,32 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
             v[q * RF + t] = x;
         }
     }
-    run_steps_from<F, Tl, INV, 0, true>(v, lds, a.tb, stw);
+    if constexpr (LUT) {
+        // step 0 (radix 16, no twiddles): table lookups, then the last two layers
+        __syncthreads();  // the table
+#pragma unroll
+        for (int q = 0; q < GF; ++q) {
+            T u[16];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const uint32_t *b = &bt[q * 16 + bitrev<4>(g)];
+                const uint32_t idx = b[0] | (b[4] << 1) | (b[8] << 2) | (b[12] << 3);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) u[4 * g + k] = lut[4 * idx + k];
+            }
+            dft_layer_k<F, 16, 8, 0>(u);
+            dft_layer_k<F, 16, 16, 0>(u);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[q * 16 + k] = u[k];
+        }
+        static_assert(Tl::NSTEPS >= 2 && Tl::span(0, false) == 1, "step 0 is followed by an exchange");
+        __syncthreads();
+        step_store_lds<F, Tl, 16>(v, lds, 1);
+        __syncthreads();
+        run_steps_from<F, Tl, false, 1, true>(v, lds, a.tb, stw);
+    } else {
+        run_steps_from<F, Tl, INV, 0, true>(v, lds, a.tb, stw);
+    }
 #pragma unroll
     for (int q = 0; q < GL; ++q) {
         int c, j;
