@@ -258,9 +258,14 @@ struct Tile {
         !LT ? 0 : STRIDED ? step_twiddle_words(LGR, ORDER, true) : step_twiddle_dir_words(LGR, ORDER, false, false);
     static_assert(!LT || NSTEPS >= 2, "the LDS twiddles are first read after the first step's barrier");
 
+    // 64-bit strided tiles exchange values between steps through LDS in two 32-bit
+    // halves, so that the tile takes half the LDS and twice the workgroups fit a CU
+    // (256 rows and more: the smaller tiles would spill at that occupancy)
+    static constexpr bool HALFX = STRIDED && sizeof(T) == 8 && LGR >= 8;
     // contiguous tiles pad one word per 16 so that power-of-two strides spread over banks
     static constexpr int RP = STRIDED ? R : R + R / 16;
-    static constexpr int LDS_WORDS = (STRIDED ? C * R : C * RP) + STW_WORDS;
+    static constexpr int TILE_WORDS = STRIDED ? (HALFX ? C * R / 2 : C * R) : C * RP;
+    static constexpr int LDS_WORDS = TILE_WORDS + STW_WORDS;
     // Waves per SIMD that strided kernels promise the register allocator: as
     // many as the LDS admits (160 KiB per CU, 4 SIMDs), at most 8. A register
     // count above that would leave LDS idle and halve the resident workgroups
@@ -308,6 +313,15 @@ __device__ inline void step_compute(typename F::T *v, const Tables &tb, const ty
     }
 }
 
+template <class Tl, class = void>
+struct HasHalfx : std::false_type {};
+template <class Tl>
+struct HasHalfx<Tl, std::void_t<decltype(Tl::HALFX)>> : std::integral_constant<bool, Tl::HALFX> {};
+template <class Tl>
+__host__ __device__ constexpr bool tile_halfx() {
+    return HasHalfx<Tl>::value;
+}
+
 template <class F, class Tl, int RAD>
 __device__ inline void step_load_lds(typename F::T *v, const typename F::T *lds) {
     constexpr int GPT = Tl::EPT / RAD;
@@ -334,6 +348,43 @@ __device__ inline void step_store_lds(const typename F::T *v, typename F::T *lds
     }
 }
 
+// The exchange between a step of radix RAD and span NS and the next step (radix
+// RADN) in two rounds of 32-bit halves through an LDS tile of C R 32-bit words:
+// low halves out in the old layout and in to the new, then the high halves.
+template <class F, class Tl, int RAD, int NS, int RADN>
+__device__ inline void exchange_halves(typename F::T *v, typename F::T *lds) {
+    static_assert(sizeof(typename F::T) == 8, "64-bit values");
+    uint32_t *l = (uint32_t *)lds;
+    uint32_t part[Tl::EPT];
+    __syncthreads();  // every read of the previous layout is done
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h) __syncthreads();  // the low halves are read
+#pragma unroll
+        for (int q = 0; q < Tl::EPT / RAD; ++q) {
+            int c, j;
+            Tl::template coords<RAD>(q, c, j);
+            const int jm = j & (NS - 1), d = (j - jm) * RAD + jm;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) l[Tl::lidx(c, d + t * NS)] = (uint32_t)(v[q * RAD + t] >> (32 * h));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Tl::EPT / RADN; ++q) {
+            int c, j;
+            Tl::template coords<RADN>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RADN; ++t) {
+                const uint32_t w = l[Tl::lidx(c, j + t * (Tl::R / RADN))];
+                if (h == 0)
+                    part[q * RADN + t] = w;
+                else
+                    v[q * RADN + t] = ((uint64_t)w << 32) | part[q * RADN + t];
+            }
+        }
+    }
+}
+
 // Run steps [s0, s1) of a transform whose inputs for step s0 are already in
 // registers; the outputs of step s1-1 stay in registers (positions of the
 // last-step layout if s1 == NSTEPS). LDS exchanges in between.
@@ -343,15 +394,19 @@ __device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, cons
     if constexpr (S < Tl::NSTEPS) {
         constexpr int RAD = Tl::radix(S, INV);
         constexpr int NS = Tl::span(S, INV);
-        if constexpr (S > 0) {
+        if constexpr (S > 0 && !tile_halfx<Tl>()) {
             // inputs of this step come from LDS, written by the previous step
             step_load_lds<F, Tl, RAD>(v, lds);
         }
         step_compute<F, Tl, RAD, NS, INV, LT>(v, tb, stw);
         if constexpr (S + 1 < Tl::NSTEPS) {
-            __syncthreads();  // every read of the previous layout is done
-            step_store_lds<F, Tl, RAD>(v, lds, NS);
-            __syncthreads();
+            if constexpr (tile_halfx<Tl>()) {
+                exchange_halves<F, Tl, RAD, NS, Tl::radix(S + 1, INV)>(v, lds);
+            } else {
+                __syncthreads();  // every read of the previous layout is done
+                step_store_lds<F, Tl, RAD>(v, lds, NS);
+                __syncthreads();
+            }
             run_steps_from<F, Tl, INV, S + 1, LT>(v, lds, tb, stw);
         }
     }
@@ -406,7 +461,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
     // t+12), read from a 16 x 4 table built here by the same arithmetic.
     constexpr bool LUT = BITS && RF == 16;
     using Unit = UnitOf<C>;
-    __shared__ T lds[C * R];
+    __shared__ T lds[Tl::TILE_WORDS];
     __shared__ T stw[Tl::STW_WORDS > 0 ? Tl::STW_WORDS : 1];
     __shared__ T lut[LUT ? 64 : 1];
 
@@ -511,9 +566,13 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
             for (int k = 0; k < 16; ++k) v[q * 16 + k] = u[k];
         }
         static_assert(Tl::NSTEPS >= 2 && Tl::span(0, false) == 1, "step 0 is followed by an exchange");
-        __syncthreads();
-        step_store_lds<F, Tl, 16>(v, lds, 1);
-        __syncthreads();
+        if constexpr (Tl::HALFX) {
+            exchange_halves<F, Tl, 16, 1, Tl::radix(1, false)>(v, lds);
+        } else {
+            __syncthreads();
+            step_store_lds<F, Tl, 16>(v, lds, 1);
+            __syncthreads();
+        }
         run_steps_from<F, Tl, false, 1, true>(v, lds, a.tb, stw);
     } else {
         run_steps_from<F, Tl, INV, 0, true>(v, lds, a.tb, stw);
