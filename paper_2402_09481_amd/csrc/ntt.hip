@@ -29,10 +29,14 @@
 //              S_FWD: column transform, then twiddle, in place
 //              S_INV: twiddle^-1, then inverse column transform, in place
 //              S_INV_PARITY: as S_INV, then canonical residue mod 2, packed
+//              (the last inverse pass also applies L^-1 and computes only the
+//              rows that hold output coefficients)
 //   contiguous C_FWD: row transform (last level of a forward transform)
 //              C_FUSED: row transform of one operand, times the other operand's
-//              spectrum (S) times L^-1, inverse row transform (last forward
-//              level, the pointwise product, first inverse level)
+//              spectrum (S), inverse row transform (last forward level, the
+//              pointwise product, first inverse level)
+//              C_PROD, C_FUSED2: the two-piece schedule's second-piece product
+//              and its first piece's fused pass with that product added
 //   small      whole extraction of one job in one workgroup (L <= 2^14)
 #include <algorithm>
 #include <cstring>

@@ -119,6 +119,27 @@ def test_last_pass_row_bounds(ctx, ctx_gl, field, n, m):
     run_case(ctx if field == "default" else ctx_gl, "toeplitz", n, m, "paper", seed=19 * n + m, px=0.4)
 
 
+def test_64bit_1024_row_columns(ctx, ctx_gl):
+    """A transform of 2^23 on the 64-bit field splits as a strided level of 2^10
+    rows (the column tile exchanged through LDS in 32-bit halves) and a row level
+    of 2^13: sampled output words against the oracle, one row at a time, and the
+    whole output against the 32-bit field's plan for the same length (the same
+    integers, so the same bits)."""
+    n, m = (1 << 22) - 5, (1 << 21) + 3  # n + m - 1 > 2^22: transform length 2^23
+    g = W.rng(23)
+    x, y = W.bernoulli_bits(g, n, 0.4), W.bernoulli_bits(g, n + m - 1, 0.5)
+    show_case("toeplitz 64-bit 2^23", n, m)
+    code, z = gpu_extract(ctx_gl, "toeplitz", x, y, n, m)
+    assert code == 0
+    nw = z.size
+    for w in sorted({0, 1, nw // 2, nw - 2, nw - 1} | {int(v) for v in g.integers(0, nw - 1, 3)}):
+        cnt = min(64, m - 64 * w)
+        want = oracle.toeplitz_rows(x, y, n, m, 64 * w, cnt)
+        assert int(z[w]) == int(want[0]), "word %d" % w
+    code32, z32 = gpu_extract(ctx, "toeplitz", x, y, n, m)
+    assert code32 == 0 and np.array_equal(z, z32)
+
+
 @pytest.mark.parametrize("n,m", [(11, 5), (13, 13), (61, 60), (1019, 500), (4099, 4099), (8219, 8000),
                                  (16421, 9000), (65587, 32768)])
 def test_dodis(ctx, n, m):
