@@ -898,11 +898,13 @@ __host__ __device__ inline uint64_t embed_word(const Emb &e, uint64_t L, uint64_
 
 __global__ void __launch_bounds__(256) k_embed(const JobDev *jobs, JobDev one) {
     const JobDev &J = jobs ? jobs[blockIdx.y] : one;
-    const uint64_t nw = J.L >> 6;
+    // (the descriptor is read once: the stores could alias it)
+    const uint64_t L = J.L, nw = L >> 6;
     const int which = blockIdx.z;
-    const Emb &e = which ? J.ey : J.ex;
+    const Emb e = which ? J.ey : J.ex;
+    uint64_t *const dst = J.eb[which];
     for (uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * 256)
-        J.eb[which][w] = embed_word(e, J.L, w);
+        gstore(dst + w, embed_word(e, L, w));
 }
 
 // ------------------------------------------------------------------ persistent batch of small jobs
