@@ -814,19 +814,36 @@ __device__ inline void small_body(const JobDev &J, bool write, uint32_t *lds, ui
     __syncthreads();
     const bool degen = J.degen_n && (red[0] == 0 || red[1] == 0);
     if (write) {
-        const uint64_t nwm = (J.m + 63) >> 6;
-        for (uint64_t w = lt; w < nwm; w += NT) {
-            uint64_t word = 0;
-            if (!degen) {
-                for (int b = 0; b < 64; ++b) {
-                    uint64_t i = w * 64 + b;
-                    if (i >= J.m) break;
-                    uint32_t bit = lds[Tl::lidx(0, (int)i)] & 1u;
-                    if (J.nfold) bit ^= lds[Tl::lidx(0, (int)(i + J.nfold))] & 1u;
-                    word |= (uint64_t)bit << b;
+        const uint64_t m = J.m, nfold = J.nfold;
+        uint64_t *const z = J.z;
+        const uint64_t nwm = (m + 63) >> 6;
+        if constexpr (NT >= 64) {
+            // a group of whole waves: word w is one ballot of coefficients 64 w ..
+            const int lane = lt & 63;
+            for (uint64_t w = (uint64_t)(lt >> 6); w < nwm; w += NT / 64) {
+                const uint64_t i = w * 64 + lane;
+                uint32_t bit = 0;
+                if (!degen && i < m) {
+                    bit = lds[Tl::lidx(0, (int)i)] & 1u;
+                    if (nfold) bit ^= lds[Tl::lidx(0, (int)(i + nfold))] & 1u;
                 }
+                const uint64_t word = __ballot(bit);
+                if (lane == 0) z[w] = word;
             }
-            J.z[w] = word;
+        } else {
+            for (uint64_t w = lt; w < nwm; w += NT) {
+                uint64_t word = 0;
+                if (!degen) {
+                    for (int b = 0; b < 64; ++b) {
+                        const uint64_t i = w * 64 + b;
+                        if (i >= m) break;
+                        uint32_t bit = lds[Tl::lidx(0, (int)i)] & 1u;
+                        if (nfold) bit ^= lds[Tl::lidx(0, (int)(i + nfold))] & 1u;
+                        word |= (uint64_t)bit << b;
+                    }
+                }
+                z[w] = word;
+            }
         }
         if (lt == 0 && J.status) *J.status = degen ? -3 : 0;
     }
