@@ -147,15 +147,6 @@ __device__ inline void dft_reg(typename F::T *v, bool inv) {
     for (int k = 0; k < RAD; ++k) v[k] = u[inv ? ((RAD - k) & (RAD - 1)) : k];
 }
 
-// Twiddle w_max^E (E < 2^LGMAX) from the two-level tables.
-template <class F>
-__device__ inline typename F::T twiddle(const Tables &tb, uint64_t E) {
-    using T = typename F::T;
-    const T *lo = (const T *)tb.lo;
-    const T *hi = (const T *)tb.hi;
-    return F::tw_combine(hi[E >> 16], lo[E & 0xFFFF]);
-}
-
 // ------------------------------------------------------------------ tile geometry
 
 // Radix of step s of a 2^lgr-point transform done in radix-16 Stockham steps
