@@ -34,15 +34,16 @@ EDEGENERATE = -3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "gf2x.c")]
 _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c with gcc into liboracle.so next to it."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+    """Compile oracle.c and gf2x.c with gcc into liboracle.so next to them."""
+    stale = not os.path.exists(_SO) or any(os.path.getmtime(_SO) < os.path.getmtime(s) for s in _SRCS)
+    if force or stale:
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-pthread", "-o", tmp] + _SRCS)
         os.replace(tmp, _SO)
     return _SO
 
@@ -61,6 +62,21 @@ def _load():
         lib.oracle_circulant_rows.argtypes = [u64p, u64, u64p, u64, u64, u64p]
         lib.oracle_von_neumann_bits.argtypes = [u64p, u64, u64p]
         lib.oracle_von_neumann_bits.restype = ctypes.c_uint64
+        sz = ctypes.c_size_t
+        lib.gf2_force_software.argtypes = [ctypes.c_int]
+        lib.gf2_force_software.restype = ctypes.c_int
+        lib.gf2_clmul64.argtypes = [u64, u64, u64p, u64p]
+        lib.gf2_clmul64.restype = None
+        lib.gf2_set_threads_depth.argtypes = [ctypes.c_int]
+        lib.gf2_set_threads_depth.restype = None
+        lib.gf2_mul.argtypes = [u64p, sz, u64p, sz, u64p]
+        lib.gf2_toeplitz_linear.argtypes = [u64p, u64, u64p, u64, u64p]
+        lib.gf2_toeplitz_block.argtypes = [u64p, u64, u64p, u64, u64, u64, u64p]
+        lib.gf2_paper_to_linear.argtypes = [u64p, u64, u64, u64p]
+        lib.gf2_circulant_rows.argtypes = [u64p, u64, u64p, u64, u64p]
+        for f in (lib.gf2_mul, lib.gf2_toeplitz_linear, lib.gf2_toeplitz_block, lib.gf2_paper_to_linear,
+                  lib.gf2_circulant_rows):
+            f.restype = ctypes.c_int
         for f in (lib.oracle_toeplitz_bits, lib.oracle_dodis_bits, lib.oracle_circulant_bits,
                   lib.oracle_toeplitz_rows, lib.oracle_dodis_rows, lib.oracle_circulant_rows):
             f.restype = None
@@ -270,3 +286,103 @@ def von_neumann(x, n: int):
     if m == 0:
         return EDEGENERATE, out[:0], 0
     return OK, out[: _nw(m)], m
+
+
+# ------------------------------------------------------------------ whole outputs as GF(2)[t] products
+
+def gf2_force_software(on: bool) -> bool:
+    """Use the shift-and-XOR carry-less product instead of the CPU instruction (a
+    testing aid); returns whether the instruction is available."""
+    return bool(_load().gf2_force_software(int(bool(on))))
+
+
+def gf2_set_threads_depth(depth: int) -> None:
+    """Top levels of the Karatsuba recursion that run on threads (3^depth leaves)."""
+    _load().gf2_set_threads_depth(int(depth))
+
+
+def clmul64(a: int, b: int) -> int:
+    """Carry-less product of two 64-bit words as a 128-bit int."""
+    lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
+    _load().gf2_clmul64(int(a), int(b), ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value | (hi.value << 64)
+
+
+def gf2_mul(a, b) -> np.ndarray:
+    """Product of two GF(2)[t] polynomials given as packed words (bit k = coefficient
+    of t^k); len(a) + len(b) words."""
+    aa = np.ascontiguousarray(np.asarray(a, dtype=np.uint64))
+    bb = np.ascontiguousarray(np.asarray(b, dtype=np.uint64))
+    r = np.zeros(aa.size + bb.size + 1, np.uint64)
+    if _load().gf2_mul(_p(aa), aa.size, _p(bb), bb.size, _p(r)) != 0:
+        raise MemoryError("gf2_mul")
+    return r[: aa.size + bb.size]
+
+
+def _linear_seed(y, N: int, m: int, seed_order: str) -> np.ndarray:
+    yy = _masked(y, N)
+    if seed_order == "linear":
+        return yy
+    s = np.zeros(_nw(N) + 1, np.uint64)
+    if _load().gf2_paper_to_linear(_p(yy), N, m, _p(s)) != 0:
+        raise MemoryError("gf2_paper_to_linear")
+    return s
+
+
+def toeplitz_product(x, y, n: int, m: int, seed_order: str = "paper", block_bits: int = 0, progress=None):
+    """(code, z): the whole Toeplitz output as the coefficients t^(n-1) .. t^(n+m-2)
+    of X(t) S(t) over GF(2) (S the seed in the linear order), by Karatsuba.
+    block_bits > 0 splits the sum over input positions into shares of that many
+    positions (a multiple of 64), XORed together; progress(done, total) is called
+    after each share."""
+    code = check("toeplitz", n, m)
+    if code:
+        return code, None
+    n, m = int(n), int(m)
+    N = n + m - 1
+    s = _linear_seed(y, N, m, seed_order)
+    xx = _masked(x, n)
+    z = np.zeros(_nw(m) + 1, np.uint64)
+    w = n if block_bits <= 0 else max(64, (int(block_bits) // 64) * 64)
+    for j0 in range(0, n, w):
+        k = min(w, n - j0)
+        if _load().gf2_toeplitz_block(_p(xx), n, _p(s), m, j0, k, _p(z)) != 0:
+            raise MemoryError("gf2_toeplitz_block")
+        if progress is not None:
+            progress(j0 + k, n)
+    return OK, z[: _nw(m)]
+
+
+def _circulant_product(a, n: int, y, m: int) -> np.ndarray:
+    aa, yy = _masked(a, n), _masked(y, n)
+    z = np.zeros(_nw(m) + 1, np.uint64)
+    if _load().gf2_circulant_rows(_p(aa), int(n), _p(yy), int(m), _p(z)) != 0:
+        raise MemoryError("gf2_circulant_rows")
+    return z[: _nw(m)]
+
+
+def dodis_product(x, y, n: int, m: int):
+    """(code, z): Dodis et al. as the cyclic convolution (length n) of the reflected
+    input b_k = x_(-k mod n) with y over GF(2), by Karatsuba."""
+    code = check("dodis", n, m, x)
+    if code:
+        return code, None
+    return OK, _circulant_product(x, n, y, m)
+
+
+def circulant_product(x, y, n_in: int, m: int):
+    """(code, z): Circulant as the cyclic convolution of length n_in + 1 with the
+    generator x' = [x, 0] (the input's bits beyond n_in read as zero)."""
+    code = check("circulant", n_in, m)
+    if code:
+        return code, None
+    return OK, _circulant_product(_masked(x, n_in), int(n_in) + 1, y, m)
+
+
+def extract_product(kind: str, x, y, n: int, m: int, seed_order: str = "paper"):
+    """Whole output of any convolution extractor through the GF(2)[t] products."""
+    if kind == "toeplitz":
+        return toeplitz_product(x, y, n, m, seed_order)
+    if kind == "circulant":
+        return circulant_product(x, y, n, m)
+    return dodis_product(x, y, n, m)
