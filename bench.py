@@ -19,9 +19,13 @@ Printed as one JSON line (rank 0). Besides the headline it reports:
   cpu_ntt       a single-threaded CPU NTT convolution, scaled to the headline;
   small_configs the small Toeplitz workload's call latency (p50/p99) and the
                 Dodis workload's time per call (skip with --no-small);
-  --batched     the 4096-block batched workload: extract_batch vs one call
-                sequence per block on the same GPU;
-  --serving     a short open-loop Poisson serving run (p50/p99 latency).
+  oracle_check  the timed extraction's first output bits against the oracle
+                rows of the CPU leg (the run exits with status 3 on a mismatch);
+  batched       the 4096-block batched workload: extract_batch vs one call
+                sequence per block on the same GPU, outputs compared, and the
+                oracle's rows on sampled blocks (skip with --no-batched);
+  serving       open-loop Poisson serving at two offered rates, p50/p99 latency
+                and output Mbit/s (--serving: the full sweep; --no-serving).
 """
 from __future__ import annotations
 
@@ -36,6 +40,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CHECK_WORDS = 64  # leading output words kept for the check against the oracle rows
 METRIC = "output Mbit/s at Toeplitz n=2^30; batched-vs-per-block speedup; p99 latency"
 
 
@@ -151,25 +156,59 @@ def profiled_vn_traffic(n: int):
     return None if e is None else e["read_bytes"] + e["write_bytes"]
 
 
-def cpu_ntt_baseline(lg: int = 22):
+def cpu_ntt_baseline(lg: int = 22, batch_sample: int = 48):
     """The single-threaded CPU NTT (`baseline/`, the 64-bit prime of the headline
-    configuration) timed on a Toeplitz extraction whose transform is 2^lg (n = 2^(lg-1),
-    m = 2^(lg-2)), and its time scaled to the headline's 2^31 transform by L log L."""
+    configuration) timed on: a Toeplitz extraction whose transform is 2^lg
+    (n = 2^(lg-1), m = 2^(lg-2)), scaled to the headline's 2^31 transform by
+    L log L; the small Toeplitz workload (n = 4096) and the Dodis workload's shape
+    (n = 1,048,589, m = 2^19, run as the Toeplitz extraction of the same lengths:
+    the same transform and work) in full; and a seeded sample of the batched
+    workload's blocks, scaled to all 4096 blocks by their sum of L log L."""
+    import math
+
     import baseline
     import workloads as W
     n, m = 1 << (lg - 1), 1 << (lg - 2)
     g = W.rng(W.BASE_SEED + 12)
     x, y = W.bernoulli_bits(g, n, 0.4), W.bernoulli_bits(g, n + m - 1, 0.5)
     baseline.toeplitz(x[:1], y[:1], 1, 1)  # build and load outside the timing
-    t0 = time.perf_counter()
-    baseline.toeplitz(x, y, n, m)
-    dt = time.perf_counter() - t0
+
+    def timed(xx, yy, nn, mm, order="paper"):
+        t0 = time.perf_counter()
+        baseline.toeplitz(xx, yy, nn, mm, order)
+        return time.perf_counter() - t0
+
+    dt = timed(x, y, n, m)
     L, LH = 1 << lg, 1 << 31
     t_head = dt * (LH * 31) / (L * lg)
-    return {"value": round(m / dt / 1e6, 3), "unit": "Mbit/s", "cores": 1, "kind": "cpu_ntt",
-            "sample": "Toeplitz n=2^%d, m=2^%d, transform 2^%d over 2^64-2^32+1, %.2f s" % (lg - 1, lg - 2, lg, dt),
-            "headline_extrapolated": {"value": round((1 << 29) / t_head / 1e6, 3), "unit": "Mbit/s",
-                                      "seconds": round(t_head, 1), "scaling": "L log2 L to L = 2^31"}}
+    out = {"value": round(m / dt / 1e6, 3), "unit": "Mbit/s", "cores": 1, "kind": "cpu_ntt",
+           "sample": "Toeplitz n=2^%d, m=2^%d, transform 2^%d over 2^64-2^32+1, %.2f s" % (lg - 1, lg - 2, lg, dt),
+           "headline_extrapolated": {"value": round((1 << 29) / t_head / 1e6, 3), "unit": "Mbit/s",
+                                     "seconds": round(t_head, 1), "scaling": "L log2 L to L = 2^31"}}
+    sm = W.toeplitz_small()
+    t = min(timed(sm.x, sm.y, sm.n, sm.m, "linear") for _ in range(20))
+    out["toeplitz_4096"] = {"us_per_call": round(t * 1e6, 1), "output_Mbit_s": round(sm.m / t / 1e6, 2)}
+    d = W.dodis_2p20()
+    t = timed(d.x, d.y, d.n, d.m)
+    out["dodis_1048589_shape"] = {"ms_per_call": round(t * 1e3, 2), "output_Mbit_s": round(d.m / t / 1e6, 3)}
+    params = W.batch_params(4096, next_na=lambda v: v)  # lengths only (no primality needed for timing)
+    lgs = [max(6, math.ceil(math.log2(n_ + m_ - 1))) for (_, n_, m_, _, _) in params]
+    cost = lambda k: (1 << k) * k  # noqa: E731
+    pick = sorted(int(i) for i in W.rng(W.BASE_SEED + 13).choice(len(params), size=batch_sample, replace=False))
+    t_s, m_s = 0.0, 0
+    for i in pick:
+        _, n_, m_, px, sub = params[i]
+        j = W.make_job("toeplitz", n_, m_, px, sub)
+        t_s += timed(j.x, j.y, n_, m_)
+        m_s += m_
+    scale = sum(cost(k) for k in lgs) / sum(cost(lgs[i]) for i in pick)
+    t_all = t_s * scale
+    sum_m = sum(p_[2] for p_ in params)
+    out["batched_4096_extrapolated"] = {"value": round(sum_m / t_all / 1e6, 3), "unit": "Mbit/s",
+                                        "seconds": round(t_all, 1),
+                                        "sample": "%d seeded blocks in %.1f s, scaled by sum of L log2 L"
+                                                  % (len(pick), t_s)}
+    return out
 
 
 def cpu_baseline(job, seconds: float):
@@ -183,14 +222,26 @@ def cpu_baseline(job, seconds: float):
     t2 = time.perf_counter()
     per_row = max(((t2 - t1) - (t1 - t0)) / 32, 1e-4)
     setup = max((t1 - t0) - 2 * per_row, 0.0)
-    rows = int(max(8, min(1 << 16, (seconds - setup) / per_row)))
+    rows = int(max(8, min(64 * CHECK_WORDS, (seconds - setup) / per_row)))
     t0 = time.perf_counter()
-    oracle.toeplitz_rows(job.x, job.y, job.n, job.m, 0, rows, job.seed_order)
+    got = oracle.toeplitz_rows(job.x, job.y, job.n, job.m, 0, rows, job.seed_order)
     dt = time.perf_counter() - t0
     return {"value": rows / dt / 1e6, "unit": "Mbit/s", "cores": 1, "kind": "oracle",
             "sample": "output bits z_0..z_%d of the n=2^30, m=2^29 Toeplitz extraction computed row by row by the "
                       "schoolbook GF(2) oracle in %.1f s (one call, setup included); rate scaled to Mbit/s"
-                      % (rows - 1, dt)}
+                      % (rows - 1, dt)}, rows, got
+
+
+def check_rows(z_head, rows: int, want) -> dict:
+    """The GPU's first `rows` output bits of the timed extraction against the oracle
+    rows the CPU leg computed (bit for bit)."""
+    import numpy as np
+    nw = (rows + 63) // 64
+    got = np.array(z_head[:nw], dtype=np.uint64)
+    if rows % 64:
+        got[-1] &= np.uint64((1 << (rows % 64)) - 1)
+    same = bool(np.array_equal(got, np.asarray(want, dtype=np.uint64)[:nw]))
+    return {"rows": rows, "bits_equal": same}
 
 
 def run_headline(args):
@@ -212,18 +263,31 @@ def run_headline(args):
     for _ in range(args.warmup):
         ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream, single_transform=True)
     torch.cuda.synchronize()
-    ctx.profile(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    log("timed x%d" % args.steps)
+    log("timed x%d (tracing off)" % args.steps)
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
         ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream, single_transform=True)
     e1.record(stream)
     torch.cuda.synchronize()
-    ctx.profile(False)
     ms = e0.elapsed_time(e1) / args.steps
+    # per-kernel durations: the same steps again with every launch bracketed by HIP
+    # events on the launch stream (a separate run, so that the events do not sit in
+    # the timed steps)
+    log("traced x%d (per-kernel durations)" % args.steps)
+    ctx.profile(True)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(args.steps):
+        ctx.extract("toeplitz", x, y, job.n, job.m, z=z, stream=stream, single_transform=True)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ctx.profile(False)
+    traced_ms = t0.elapsed_time(t1) / args.steps
     marks = ctx.profile_read()
+    # the first output words, for the check against the oracle rows of the CPU leg
+    z_head = z[:CHECK_WORDS].cpu().numpy().view(np.uint64).copy()
 
     L = 1 << 31
     w = 8
@@ -267,6 +331,7 @@ def run_headline(args):
                  "frac_of_hbm_roofline": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                  "roofline_Mbit_s": round(job.m / (path_bytes / (HBM_PEAK_GBS * 1e9)) / 1e6, 1)},
         "kernels": kernels,
+        "traced_ms_per_step": round(traced_ms, 3),
         "paper_context": "paper: ~1 Mbit/s below n=2^29 and 3-4x lower above (64-bit-class prime), Apple M2 Max CPU",
     }
     # both fractions, and the one that binds (the higher)
@@ -295,7 +360,7 @@ def run_headline(args):
     ctx.close()
     del x, y, z
     torch.cuda.empty_cache()
-    return out, job
+    return out, job, z_head
 
 
 def run_two_piece(ctx, job, x, y, z, stream, args, single_ms):
@@ -342,7 +407,8 @@ def run_batched(log, count=4096, reps=3):
     """The batched workload (4096 Toeplitz/Circulant blocks, n log-uniform in
     [2^10, 2^22], m = n/2): extract_batch (one persistent launch for the
     single-workgroup sizes plus grouped multi-pass launches, replayed from a HIP
-    graph) against one extraction call sequence per block, same jobs, same GPU."""
+    graph) against one extraction call sequence per block, same jobs, same GPU.
+    Returns the summary, the jobs and the batched outputs (host copies)."""
     import numpy as np
     import torch
 
@@ -375,9 +441,11 @@ def run_batched(log, count=4096, reps=3):
     log("batched: warmup")
     ctx.batch(dev, sync=True, graph=True)
     ctx.batch(dev_u, sync=True, unbatched=True)
+    log("batched: timed x%d each" % reps)
     t_b = timed(lambda: ctx.batch(dev, stream=stream, graph=True), reps)
     t_u = timed(lambda: ctx.batch(dev_u, stream=stream, unbatched=True), reps)
     same = all(torch.equal(a["z"], b["z"]) for a, b in zip(dev, dev_u))
+    zs = [d["z"].cpu().numpy().view(np.uint64).copy() for d in dev]
     sum_m = sum(j.m for j in jobs)
     sum_n = sum(j.n for j in jobs)
     kinds = {k: sum(1 for j in jobs if j.kind == k) for k in ("toeplitz", "circulant")}
@@ -387,7 +455,42 @@ def run_batched(log, count=4096, reps=3):
     return {"blocks": count, "kinds": kinds, "sum_n_bits": sum_n, "sum_m_bits": sum_m,
             "batched_ms": round(t_b, 3), "per_block_ms": round(t_u, 3), "speedup": round(t_u / t_b, 2),
             "batched_Mbit_s": round(sum_m / (t_b * 1e-3) / 1e6, 1),
-            "per_block_Mbit_s": round(sum_m / (t_u * 1e-3) / 1e6, 1), "outputs_identical": bool(same)}
+            "per_block_Mbit_s": round(sum_m / (t_u * 1e-3) / 1e6, 1),
+            "outputs_identical": bool(same)}, jobs, zs
+
+
+def cpu_baseline_batched(jobs, zs, blocks=128, seed=5):
+    """The CPU leg for the batched workload: the oracle's schoolbook rows (one
+    thread) on a seeded sample of blocks — the first and one random output word of
+    each — timed (rate scaled to Mbit/s), and compared with the GPU's batched
+    outputs of those words."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    g = W.rng(seed)
+    pick = sorted(int(i) for i in g.choice(len(jobs), size=min(blocks, len(jobs)), replace=False))
+    rows = 0
+    bad = []
+    t0 = time.perf_counter()
+    for i in pick:
+        j, z = jobs[i], zs[i]
+        nw = (j.m + 63) // 64
+        for w in sorted({0, int(g.integers(0, nw))}):
+            cnt = min(64, j.m - 64 * w)
+            if j.kind == "toeplitz":
+                want = oracle.toeplitz_rows(j.x, j.y, j.n, j.m, 64 * w, cnt, j.seed_order)
+            else:
+                want = oracle.circulant_rows(j.x, j.y, j.n, j.m, 64 * w, cnt)
+            got = int(z[w]) & ((1 << cnt) - 1)
+            rows += cnt
+            if got != int(want[0]):
+                bad.append((i, w))
+    dt = time.perf_counter() - t0
+    return {"value": round(rows / dt / 1e6, 4), "unit": "Mbit/s", "cores": 1, "kind": "oracle",
+            "sample": "%d output bits (the first and one random word of %d seeded blocks of all sizes) by the "
+                      "schoolbook rows in %.1f s" % (rows, len(pick), dt)}, \
+        {"blocks": len(pick), "bits": rows, "bits_equal": not bad, "mismatches": bad[:8]}
 
 
 def run_paper_shapes(log, reps=2):
@@ -548,8 +651,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0 = skip)")
-    ap.add_argument("--batched", action="store_true", help="also run the 4096-block batched comparison")
-    ap.add_argument("--serving", action="store_true", help="also run a short serving sweep")
+    ap.add_argument("--batched", action="store_true", help="(default) the 4096-block batched comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--serving", action="store_true",
+                    help="the full serving sweep (1k-50k req/s) instead of the default two offered rates")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--warm", action="store_true", help="also time the headline with the seed transform cached")
     ap.add_argument("--paper-shapes", action="store_true", help="also time the paper's QKD extraction shapes")
     ap.add_argument("--von-neumann", action="store_true", help="also time the Von Neumann extractor")
@@ -576,23 +682,42 @@ def main():
         log("copy calibration: %d bytes read + %d bytes written per copy kernel" % (nb, nb))
         del src, dst
         torch.cuda.empty_cache()
-    out, job = run_headline(args)
+    out, job, z_head = run_headline(args)
+    # the CPU leg: the oracle on a bounded sample of the same workload; its rows
+    # also check the timed extraction's first output bits
+    log("cpu baseline (oracle, %.0f s budget)" % max(args.cpu_seconds, 1.0))
+    cb, rows, want = cpu_baseline(job, max(args.cpu_seconds, 1.0))
     if args.cpu_seconds > 0:
-        log("cpu baseline (oracle, %.0f s budget)" % args.cpu_seconds)
-        out["cpu_baseline"] = cpu_baseline(job, args.cpu_seconds)
+        out["cpu_baseline"] = cb
         log("cpu NTT baseline (one thread)")
         out["cpu_ntt"] = cpu_ntt_baseline()
+    out["oracle_check"] = check_rows(z_head, rows, want)
+    if not out["oracle_check"]["bits_equal"]:
+        print(json.dumps(out), flush=True)
+        log("MISMATCH: the timed extraction's first %d output bits differ from the oracle's rows" % rows)
+        sys.exit(3)
     if not args.no_small:
         out["small_configs"] = run_small_configs(log)
-    if args.batched:
-        out["batched"] = run_batched(log)
+    if not args.no_batched:
+        b, bjobs, bzs = run_batched(log)
+        log("batched: cpu leg (oracle rows on sampled blocks)")
+        b["cpu_baseline"], b["oracle_check"] = cpu_baseline_batched(bjobs, bzs)
+        out["batched"] = b
+        del bjobs, bzs
+        if not b["oracle_check"]["bits_equal"] or not b["outputs_identical"]:
+            print(json.dumps(out), flush=True)
+            log("MISMATCH in the batched workload")
+            sys.exit(3)
     if args.paper_shapes:
         out["paper_shapes"] = run_paper_shapes(log)
     if args.von_neumann:
         out["von_neumann"] = run_von_neumann(log)
-    if args.serving:
+    if not args.no_serving:
         from paper_2402_09481_amd import serve
-        out["serving"] = serve.bench(log=log)
+        if args.serving:  # the full sweep
+            out["serving"] = serve.bench(log=log)
+        else:
+            out["serving"] = serve.bench(log=log, rates=(2000, 20000), count=400)
     if rank == 0:
         print(json.dumps(out), flush=True)
 

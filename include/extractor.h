@@ -32,7 +32,8 @@
  * The library keeps device workspace in a stream-ordered pool bounded by the
  * context's HBM budget; a call whose workspace does not fit returns
  * EXT_ENOMEM without enqueuing anything. Calls on one context may be made from
- * several host threads and on several streams.
+ * several host threads and on several streams (graph-mode batch calls,
+ * EXT_GRAPH, take their host-side steps one call at a time per context).
  */
 #ifndef PAPER_2402_09481_AMD_EXTRACTOR_H
 #define PAPER_2402_09481_AMD_EXTRACTOR_H

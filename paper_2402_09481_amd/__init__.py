@@ -56,6 +56,28 @@ def _ptr(t) -> int:
     return t.data_ptr()
 
 
+def _seed_bits(kind: str, n: int, m: int) -> int:
+    return {"toeplitz": n + m - 1, "circulant": n + 1, "dodis": n}[kind]
+
+
+def _check_len(t, nbits: int, what: str):
+    """t must hold at least ceil(nbits/64) packed words: the library takes raw device
+    pointers, so a short buffer would be read or written past its end."""
+    if t.numel() < words(nbits):
+        raise ValueError("%s holds %d words; %d bits need %d" % (what, t.numel(), nbits, words(nbits)))
+
+
+def _status_ptr(status):
+    """Device pointer of an int32 status word on the GPU (or None)."""
+    import torch
+    if status is None:
+        return None
+    if not isinstance(status, torch.Tensor) or not status.is_cuda or status.dtype != torch.int32 \
+            or status.numel() < 1:
+        raise TypeError("status must be an int32 GPU tensor with at least one element")
+    return ctypes.c_void_p(status.data_ptr())
+
+
 def _stream_handle(stream):
     import torch
     if stream is None:
@@ -134,11 +156,19 @@ class Context:
         change while cached; see seed_cache_clear). single_transform: no two-piece
         split of large Toeplitz extractions (one transform over the 64-bit field)."""
         import torch
+        if kind not in ("toeplitz", "circulant", "dodis"):
+            raise ValueError("unknown extractor kind %r" % kind)
+        n, m = int(n), int(m)
         if z is None:
             z = torch.empty(words(m), dtype=torch.int64, device=x.device)
+        _ptr(x), _ptr(y), _ptr(z)
+        if 1 <= m <= n <= (1 << 40):  # sizes the library accepts (it rejects the others itself)
+            _check_len(x, n, "x")
+            _check_len(y, _seed_bits(kind, n, m), "y")
+            _check_len(z, m, "z")
         flags = (EXT_SEED_LINEAR if seed_order == "linear" else 0) | (EXT_SYNC if sync else 0) | \
             (_lib.EXT_SEED_CACHED if cache_seed else 0) | (_lib.EXT_SINGLE_TRANSFORM if single_transform else 0)
-        st = ctypes.c_void_p(status.data_ptr()) if status is not None else None
+        st = _status_ptr(status)
         s = _stream_handle(stream)
         if kind == "toeplitz":
             rc = self._lib.extract_toeplitz(self.handle, _ptr(x), int(n), _ptr(y), int(m), _ptr(z), flags, st, s)
@@ -164,9 +194,12 @@ class Context:
             z = torch.empty(max(1, words(int(n) // 2)), dtype=torch.int64, device=x.device)
         if m_out is None:
             m_out = torch.zeros(1, dtype=torch.int64, device=x.device)
-        if m_out.element_size() != 8 or not m_out.is_cuda:
+        if m_out.element_size() != 8 or not m_out.is_cuda or m_out.numel() < 1:
             raise TypeError("m_out must be a 64-bit GPU tensor")
-        st = ctypes.c_void_p(status.data_ptr()) if status is not None else None
+        _ptr(x), _ptr(z)
+        if 2 <= int(n) <= _lib.EXT_VN_MAX_BITS:  # sizes the library accepts
+            _check_len(x, int(n), "x")
+        st = _status_ptr(status)
         rc = self._lib.extract_von_neumann(self.handle, _ptr(x), int(n), _ptr(z), int(z.numel()),
                                            ctypes.c_void_p(m_out.data_ptr()), EXT_SYNC if sync else 0, st,
                                            _stream_handle(stream))
@@ -209,15 +242,23 @@ class Context:
         the launch sequence of this batch signature into a HIP graph and replays it."""
         arr = (ExtJob * len(jobs))()
         for i, j in enumerate(jobs):
-            arr[i].kind = KINDS[j["kind"]]
+            kind = j["kind"]
+            if kind not in ("toeplitz", "circulant", "dodis"):
+                raise ValueError("job %d: unknown extractor kind %r" % (i, kind))
+            n, m = int(j["n"]), int(j["m"])
+            arr[i].kind = KINDS[kind]
             arr[i].flags = EXT_SEED_LINEAR if j.get("seed_order") == "linear" else 0
-            arr[i].n = int(j["n"])
-            arr[i].m = int(j["m"])
+            arr[i].n = n
+            arr[i].m = m
             arr[i].x = _ptr(j["x"])
             arr[i].y = _ptr(j["y"])
             arr[i].z = _ptr(j["z"])
-            st = j.get("status")
-            arr[i].status = st.data_ptr() if st is not None else None
+            if 1 <= m <= n <= (1 << 40):
+                _check_len(j["x"], n, "job %d: x" % i)
+                _check_len(j["y"], _seed_bits(kind, n, m), "job %d: y" % i)
+                _check_len(j["z"], m, "job %d: z" % i)
+            st = _status_ptr(j.get("status"))
+            arr[i].status = st.value if st is not None else None
         fn = self._lib.extract_batch_unbatched if unbatched else self._lib.extract_batch
         flags = (EXT_SYNC if sync else 0) | (_lib.EXT_GRAPH if (graph and not unbatched) else 0)
         rc = fn(self.handle, arr, len(jobs), flags, _stream_handle(stream))

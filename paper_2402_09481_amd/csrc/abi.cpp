@@ -462,6 +462,10 @@ struct ext_ctx {
         bool ever = false;
     };
     std::map<std::string, GraphEntry> graphs;
+    // held by a graph-mode batch call from its cache lookup until its replay is
+    // enqueued: entries, their staging and the capture stream are used by one
+    // call at a time, and eviction never meets an entry in use
+    std::mutex graph_mu;
     // transformed-seed cache
     struct SeedEntry {
         char *ptr = nullptr;
@@ -504,10 +508,12 @@ bool valid_plan(const Plan &p) {
     return sum == p.lg;
 }
 
-// The built-in plan, or the context's tuned one for the same field and length.
+// The built-in plan, or the context's tuned one for the same field and length
+// (also in a context that forces a field: a tuned plan of that field applies, so
+// that every plan of every field can be run and checked).
 int plan_for(ext_ctx *c, uint64_t Lmin, Plan &p) {
     int rc = make_plan(Lmin, c ? c->force_field : 0, p);
-    if (rc != EXT_OK || !c || c->force_field) return rc;
+    if (rc != EXT_OK || !c) return rc;
     std::lock_guard<std::mutex> g(c->mu);
     auto it = c->tuned.find(p.field * 64 + p.lg);
     if (it != c->tuned.end()) p = it->second;
@@ -1564,6 +1570,7 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
     const size_t desc_bytes = align256(ndesc * sizeof(JobDev));
     hipError_t e = hipSuccess;
     if (flags & EXT_GRAPH) {
+        std::lock_guard<std::mutex> graph_lock(c->graph_mu);
         Lease lease;
         int rc = pool_acquire(c, bl.max_ws, stream, lease);
         if (rc != EXT_OK) return rc;

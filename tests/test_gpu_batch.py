@@ -96,3 +96,44 @@ def test_batch_reports_invalid_jobs(ctx):
             continue
         assert errs[i] == 0 and sts[i] == 0
         assert np.array_equal(zs[i], oracle.extract(j.kind, j.x, j.y, j.n, j.m, j.seed_order)[1])
+
+
+def test_batched_workload_at_its_sizes():
+    """The batched workload exactly as the benchmark runs it: 4096 Toeplitz/Circulant
+    blocks, n log-uniform in [2^10, 2^22], m = n/2, one extract_batch replayed from a
+    HIP graph (twice, the second a replay). Every block's whole output against the
+    oracle: the GF(2)[t] product route for all blocks, the schoolbook rows as well
+    for n <= 2^14."""
+    import time
+
+    import torch
+
+    import paper_2402_09481_amd as P
+    show_case("batched workload: generating 4096 blocks")
+    jobs = W.batch_jobs(4096, next_na=oracle.next_na)
+    assert len(jobs) == 4096 and max(j.n for j in jobs) > (1 << 21) and min(j.n for j in jobs) < (1 << 11)
+    c = P.Context(0)
+    dev = []
+    for j in jobs:
+        dev.append({"kind": j.kind, "n": j.n, "m": j.m, "x": to_dev(j.x), "y": to_dev(j.y),
+                    "z": torch.full((W.nwords(j.m),), -1, dtype=torch.int64, device="cuda")})
+    show_case("batched workload: graph capture + replay")
+    for rep in range(2):
+        for d in dev:
+            d["z"].fill_(-1)
+        rc, errs = c.batch(dev, sync=True, graph=True)
+        assert rc == 0 and not any(errs)
+    torch.cuda.synchronize()
+    zs = [to_host(d["z"]) for d in dev]
+    t0 = time.time()
+    for i, (j, z) in enumerate(zip(jobs, zs)):
+        if i % 512 == 0:
+            show_case("batched workload: oracle block %d (%.0f s)" % (i, time.time() - t0))
+        code, want = oracle.extract_product(j.kind, j.x, j.y, j.n, j.m, j.seed_order)
+        assert code == 0
+        assert np.array_equal(z, want), (i, j.kind, j.n, j.m)
+        if j.n <= (1 << 14):
+            assert np.array_equal(z, oracle.extract(j.kind, j.x, j.y, j.n, j.m, j.seed_order)[1])
+    c.close()
+    del dev
+    torch.cuda.empty_cache()

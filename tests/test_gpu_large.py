@@ -1,9 +1,16 @@
-"""GPU parity at the full Toeplitz size (n = 2^30, m = 2^29): the library's default
-plan (two pieces, transforms of 2^30 over 3*2^30+1) against the oracle on
-sampled output words computed one row at a time, GF(2) bilinearity of the whole
-output, and the whole output of the one-transform plan (length 2^31 over the
-64-bit field) — the same integers, so the same bits."""
-import os
+"""GPU parity at the full Toeplitz size (n = 2^30, m = 2^29, paper seed order),
+for the exact call the benchmark times: the default context (tuned plans), one
+transform of length 2^31 over the 64-bit field (single_transform=True).
+
+* sampled output words against the schoolbook oracle, one row at a time
+  (first and last words, the words around the quarter and half points, random
+  words);
+* the whole 2^29-bit output against the oracle's GF(2)[t] product route
+  (Karatsuba over carry-less multiplies, no transform);
+* the whole output against the library's default plan for this shape (two
+  pieces of 2^30 over 3*2^30+1) — the same integers, so the same bits;
+* GF(2) bilinearity of the whole output."""
+import time
 
 import numpy as np
 import pytest
@@ -19,14 +26,18 @@ N_LARGE, M_LARGE = 1 << 30, 1 << 29
 
 @pytest.fixture(scope="module")
 def large():
-    import paper_2402_09481_amd as P
     import torch
+
+    import paper_2402_09481_amd as P
     ctx = P.Context(0)
+    assert ctx.tune_get(64, 31) == [9, 10, 12]  # the measured plan of the packaged tuning table
     show_case("toeplitz_large: generating inputs")
     job = W.toeplitz_large()
+    assert (job.n, job.m, job.seed_order) == (N_LARGE, M_LARGE, "paper")
     x, y = to_dev(job.x), to_dev(job.y)
-    show_case("toeplitz_large: extracting")
-    z = ctx.extract("toeplitz", x, y, job.n, job.m, sync=True)
+    show_case("toeplitz_large: the benchmarked call (one 2^31 transform, 64-bit field)")
+    z = torch.full((M_LARGE // 64,), -1, dtype=torch.int64, device="cuda")
+    ctx.extract("toeplitz", x, y, job.n, job.m, z=z, single_transform=True, sync=True)
     torch.cuda.synchronize()
     yield ctx, job, x, y, z
     del x, y, z
@@ -38,13 +49,39 @@ def test_large_sampled_words(large):
     ctx, job, x, y, z = large
     zh = to_host(z)
     assert zh.size == M_LARGE // 64
-    g = W.rng(11)
     nw = zh.size
-    words = sorted({0, 1, nw // 2 - 1, nw // 2, nw - 2, nw - 1} | {int(v) for v in g.integers(0, nw, 4)})
+    g = W.rng(11)
+    fixed = {0, 1, 2, 63, 64, nw // 4 - 1, nw // 4, nw // 2 - 1, nw // 2, 3 * nw // 4, nw - 2, nw - 1}
+    words = sorted(fixed | {int(v) for v in g.integers(0, nw, 4)})
     for w in words:
         show_case("toeplitz_large word", w)
         want = oracle.toeplitz_rows(job.x, job.y, job.n, job.m, 64 * w, 64, job.seed_order)
         assert int(zh[w]) == int(want[0]), "word %d" % w
+
+
+def test_large_whole_output_gf2_product(large):
+    ctx, job, x, y, z = large
+    show_case("toeplitz_large: whole output against the GF(2)[t] product (CPU, Karatsuba)")
+    t0 = time.time()
+
+    def progress(done, total):
+        show_case("  product: %d of %d input bits, %.0f s" % (done, total, time.time() - t0))
+
+    code, want = oracle.toeplitz_product(job.x, job.y, job.n, job.m, job.seed_order, block_bits=1 << 27,
+                                         progress=progress)
+    assert code == 0
+    got = to_host(z)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, "%d words differ, first %s" % (bad.size, bad[:8])
+
+
+def test_large_single_transform_equals_two_piece(large):
+    import torch
+    ctx, job, x, y, z = large
+    show_case("toeplitz_large: default plan (two pieces over 3*2^30+1)")
+    z2 = ctx.extract("toeplitz", x, y, job.n, job.m, sync=True)
+    assert torch.equal(z, z2)
+    del z2
 
 
 def test_large_bilinear(large):
@@ -52,25 +89,7 @@ def test_large_bilinear(large):
     ctx, job, x, y, z = large
     show_case("toeplitz_large bilinearity")
     x2 = to_dev(W.bernoulli_bits(W.rng(99), job.n, 0.5))
-    z2 = ctx.extract("toeplitz", x2, y, job.n, job.m, sync=True)
-    z3 = ctx.extract("toeplitz", torch.bitwise_xor(x, x2), y, job.n, job.m, sync=True)
+    z2 = ctx.extract("toeplitz", x2, y, job.n, job.m, sync=True, single_transform=True)
+    z3 = ctx.extract("toeplitz", torch.bitwise_xor(x, x2), y, job.n, job.m, sync=True, single_transform=True)
     assert torch.equal(torch.bitwise_xor(z, z2), z3)
     del x2, z2, z3
-
-
-def test_large_two_piece_equals_64bit_transform(large):
-    import torch
-
-    import paper_2402_09481_amd as P
-    ctx, job, x, y, z = large
-    os.environ["EXT_FORCE_FIELD"] = "gl"
-    try:
-        cgl = P.Context(0)
-    finally:
-        del os.environ["EXT_FORCE_FIELD"]
-    show_case("toeplitz_large: 64-bit single transform")
-    z64 = cgl.extract("toeplitz", x, y, job.n, job.m, sync=True)
-    assert torch.equal(z, z64)
-    del z64
-    cgl.close()
-    torch.cuda.empty_cache()

@@ -240,3 +240,25 @@ def test_sync_flag_returns_status(ctx):
     y = torch.ones(W.nwords(n), dtype=torch.int64, device="cuda")
     rc, _ = ctx.extract("dodis", x, y, n, m, sync=True, check=False)
     assert rc == oracle.EDEGENERATE
+
+
+def test_binding_rejects_short_buffers(ctx):
+    """The binding checks buffer lengths before the library sees the raw pointers."""
+    import torch
+    n, m = 1000, 300
+    x = torch.zeros(W.nwords(n), dtype=torch.int64, device="cuda")
+    y = torch.zeros(W.nwords(n + m - 1), dtype=torch.int64, device="cuda")
+    z = torch.zeros(W.nwords(m), dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError):
+        ctx.extract("toeplitz", x[:-1], y, n, m, z=z)
+    with pytest.raises(ValueError):
+        ctx.extract("toeplitz", x, y[:-1], n, m, z=z)
+    with pytest.raises(ValueError):
+        ctx.extract("toeplitz", x, y, n, m, z=z[:-1])
+    with pytest.raises(TypeError):
+        ctx.extract("toeplitz", x, y, n, m, z=z, status=torch.zeros(1, dtype=torch.int64, device="cuda"))
+    with pytest.raises(TypeError):
+        ctx.extract("toeplitz", x, y, n, m, z=z, status=torch.zeros(1, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        ctx.batch([{"kind": "toeplitz", "n": n, "m": m, "x": x, "y": y[:-2], "z": z}])
+    ctx.extract("toeplitz", x, y, n, m, z=z, sync=True)  # the full-length buffers pass

@@ -30,8 +30,12 @@ def test_all_u32_plans(lg):
     ctx.close()
 
 
-@pytest.mark.parametrize("lg", [16, 21])
+@pytest.mark.parametrize("lg", [16, 21, 22, 23, 24])
 def test_all_u64_plans(lg):
+    """Every 64-bit plan the tuner may pick (2 and 3 levels; at 2^24 the middle
+    strided levels of 2^10 rows that the 2^31 plan uses), each against the whole
+    output of the oracle, for two shapes: m = L/4 as in the large workload
+    (the last inverse pass computes a quarter of its rows) and m just above L/4."""
     import paper_2402_09481_amd as P
     from paper_2402_09481_amd.tune import candidates
     os.environ["EXT_FORCE_FIELD"] = "gl"
@@ -39,15 +43,20 @@ def test_all_u64_plans(lg):
         ctx = P.Context(0, tune=False)
     finally:
         del os.environ["EXT_FORCE_FIELD"]
-    n = (1 << (lg - 1)) - 5
-    m = (1 << (lg - 2)) + 3
+    cands = candidates(64, lg)
+    assert cands, lg
     g = W.rng(lg + 100)
-    x, y = W.bernoulli_bits(g, n, 0.4), W.bernoulli_bits(g, n + m - 1, 0.5)
-    want = oracle.extract("toeplitz", x, y, n, m)[1]
-    # a forced-field context has no tuned plans; check the default split and a few others
-    import paper_2402_09481_amd as P2  # noqa: F401
-    code, z = gpu_extract(ctx, "toeplitz", x, y, n, m)
-    assert code == 0 and np.array_equal(z, want)
+    for n, m in ((1 << (lg - 1), 1 << (lg - 2)), ((1 << (lg - 1)) - 5, (1 << (lg - 2)) + 3)):
+        x, y = W.bernoulli_bits(g, n, 0.4), W.bernoulli_bits(g, n + m - 1, 0.5)
+        want = oracle.toeplitz_product(x, y, n, m, "paper")[1]
+        if lg <= 16:
+            assert np.array_equal(want, oracle.extract("toeplitz", x, y, n, m)[1])
+        for lv in cands:
+            ctx.tune_set(64, lg, lv)
+            assert ctx.tune_get(64, lg) == lv
+            show_case("u64 plan", lg, lv, n, m)
+            code, z = gpu_extract(ctx, "toeplitz", x, y, n, m)
+            assert code == 0 and np.array_equal(z, want), (lv, n, m)
     ctx.close()
 
 
