@@ -53,6 +53,7 @@ extern "C" {
 #define EXT_ENOMEM (-4)      /* workspace does not fit the context's HBM budget */
 #define EXT_ETOOLARGE (-5)   /* the transform length would exceed 2^32 (Von Neumann: n beyond EXT_VN_MAX_BITS) */
 #define EXT_EDEVICE (-6)     /* a HIP runtime call failed (Von Neumann: also a device-side wait that ran out) */
+#define EXT_ESCRATCH (-7)    /* extract_toeplitz_noalloc: the shape's workspace exceeds EXT_NOALLOC_SCRATCH_BYTES */
 
 /* ---- flags ---------------------------------------------------------- */
 /* Toeplitz seed order. PAPER (default): the matrix of eq. (toep) in the
@@ -128,6 +129,24 @@ int extract_circulant(ext_ctx *ctx, const uint64_t *x, uint64_t n_in, const uint
  *   flags: optionally EXT_SYNC, EXT_SEED_CACHED, EXT_SINGLE_TRANSFORM. */
 int extract_dodis(ext_ctx *ctx, const uint64_t *x, const uint64_t *y, uint64_t n, uint64_t m, uint64_t *z,
                   uint32_t flags, int32_t *status, void *stream);
+
+/* The Toeplitz extractor (as extract_toeplitz) for callers that cannot
+ * allocate memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation. It calls no hipMalloc, hipFree, hipHostMalloc or other
+ * allocating routine: its workspace is a fixed array of EXT_NOALLOC_SCRATCH_BYTES
+ * in device memory, one per GPU, held from the first ext_create on that GPU until
+ * the process ends. The caller still passes x, y and z (device pointers).
+ *   Shapes whose workspace does not fit the array return EXT_ESCRATCH (transforms
+ *   up to 2^22, i.e. n + m - 1 <= 2^22, fit; up to 2^14 need none). flags:
+ *   EXT_SEED_PAPER | EXT_SEED_LINEAR, optionally | EXT_SYNC (without a status
+ *   pointer the status word is kept in the array). Launches are not traced.
+ *   Every call on one GPU uses that GPU's one array: calls that overlap in time on
+ *   one GPU (other streams, other threads, other contexts) race and give wrong
+ *   results; order them (one stream, or events). Each call writes every part of
+ *   the array it reads, so no call depends on what an earlier call left. */
+#define EXT_NOALLOC_SCRATCH_BYTES (((size_t)40) << 20)
+int extract_toeplitz_noalloc(ext_ctx *ctx, const uint64_t *x, uint64_t n, const uint64_t *y, uint64_t m,
+                             uint64_t *z, uint32_t flags, int32_t *status, void *stream);
 
 /* Von Neumann extractor (section "Von Neumann": for every pair
  * (x_{2j}, x_{2j+1}), j < floor(n/2), in order of j, output x_{2j} when the two

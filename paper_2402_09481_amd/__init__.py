@@ -151,10 +151,12 @@ class Context:
     # -- raw calls (device tensors in, device tensor out) --------------------------------
     def extract(self, kind: str, x, y, n: int, m: int, z=None, seed_order: str = "paper", sync: bool = False,
                 status=None, stream=None, check: bool = True, cache_seed: bool = False,
-                single_transform: bool = False) -> "object":
+                single_transform: bool = False, no_alloc: bool = False) -> "object":
         """cache_seed: keep / reuse the seed's transform (the seed bits at y must not
         change while cached; see seed_cache_clear). single_transform: no two-piece
-        split of large Toeplitz extractions (one transform over the 64-bit field)."""
+        split of large Toeplitz extractions (one transform over the 64-bit field).
+        no_alloc: Toeplitz through extract_toeplitz_noalloc (the library's fixed
+        per-GPU workspace; calls on one GPU must not overlap)."""
         import torch
         if kind not in ("toeplitz", "circulant", "dodis"):
             raise ValueError("unknown extractor kind %r" % kind)
@@ -170,7 +172,12 @@ class Context:
             (_lib.EXT_SEED_CACHED if cache_seed else 0) | (_lib.EXT_SINGLE_TRANSFORM if single_transform else 0)
         st = _status_ptr(status)
         s = _stream_handle(stream)
-        if kind == "toeplitz":
+        if no_alloc:
+            if kind != "toeplitz" or cache_seed or single_transform:
+                raise ValueError("no_alloc: Toeplitz only, without cache_seed / single_transform")
+            rc = self._lib.extract_toeplitz_noalloc(self.handle, _ptr(x), int(n), _ptr(y), int(m), _ptr(z), flags,
+                                                    st, s)
+        elif kind == "toeplitz":
             rc = self._lib.extract_toeplitz(self.handle, _ptr(x), int(n), _ptr(y), int(m), _ptr(z), flags, st, s)
         elif kind == "circulant":
             rc = self._lib.extract_circulant(self.handle, _ptr(x), int(n), _ptr(y), int(m), _ptr(z), flags, st, s)

@@ -18,6 +18,8 @@ EXT_EDEGENERATE = -3
 EXT_ENOMEM = -4
 EXT_ETOOLARGE = -5
 EXT_EDEVICE = -6
+EXT_ESCRATCH = -7
+EXT_NOALLOC_SCRATCH_BYTES = 40 << 20
 
 EXT_SEED_PAPER = 0
 EXT_SEED_LINEAR = 1
@@ -42,6 +44,7 @@ SYMBOLS = [
     "ext_mem_stats", "ext_trim", "ext_is_na_prime", "ext_next_na", "ext_closest_na",
     "ext_strerror", "ext_version", "ext_profile", "ext_profile_read",
     "ext_tune_set", "ext_tune_get", "ext_tune_save", "ext_seed_cache_clear", "extract_von_neumann",
+    "extract_toeplitz_noalloc",
 ]
 
 
@@ -85,7 +88,8 @@ def load() -> ctypes.CDLL:
     lib.extract_toeplitz.argtypes = [vp, vp, u64, vp, u64, vp, u32, vp, vp]
     lib.extract_circulant.argtypes = [vp, vp, u64, vp, u64, vp, u32, vp, vp]
     lib.extract_dodis.argtypes = [vp, vp, vp, u64, u64, vp, u32, vp, vp]
-    for f in (lib.extract_toeplitz, lib.extract_circulant, lib.extract_dodis):
+    lib.extract_toeplitz_noalloc.argtypes = [vp, vp, u64, vp, u64, vp, u32, vp, vp]
+    for f in (lib.extract_toeplitz, lib.extract_circulant, lib.extract_dodis, lib.extract_toeplitz_noalloc):
         f.restype = ctypes.c_int
     lib.extract_von_neumann.argtypes = [vp, vp, u64, vp, u64, vp, u32, vp, vp]
     lib.extract_von_neumann.restype = ctypes.c_int

@@ -448,6 +448,7 @@ struct ext_ctx {
     Tables tb[NFIELDS];
     void *tb_mem[NFIELDS][3] = {};
     int force_field = 0;
+    void *scratch = nullptr;  // this device's allocation-free workspace (noalloc_scratch_address)
     std::map<int, Plan> tuned;  // key: field * 64 + lg
     hipStream_t capture_stream = nullptr;
     // pinned status words for EXT_SYNC calls without a status pointer
@@ -654,6 +655,8 @@ struct Tracer {
         }
         hipEventRecord(a, s);
     }
+    // (labels are built only when tracing is on: `if (tr.on) tr.end(...)`, so
+    // that an untraced launch sequence makes no host allocation)
     void end(const std::string &label) {
         if (!on || !a) return;
         hipEvent_t b = nullptr;
@@ -692,14 +695,14 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
     if (p.small) {
         tr.begin();
         hipError_t e = launch_small(p.lg, njobs, jobs_dev, one, tb, s);
-        tr.end(pass_label("small", p.field, p.lg, 0));
+        if (tr.on) tr.end(pass_label("small", p.field, p.lg, 0));
         return e;
     }
     const uint64_t L = uint64_t(1) << p.lg;
     hipError_t e;
     tr.begin();
     e = launch_embed(njobs, L, jobs_dev, one, s);
-    tr.end("embed");
+    if (tr.on) tr.end("embed");
     if (e != hipSuccess) return e;
     // arrays: `fwd` lists the operands transformed here; the fused pass runs on `fused`
     const int fused = ph == PH_WARM ? 0 : 1;
@@ -722,7 +725,7 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
             pl.one = one;
             tr.begin();
             e = launch_strided(pl, tb, s);
-            tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, which));
+            if (tr.on) tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, which));
             if (e != hipSuccess) return e;
             Mprev = pl.S;
         }
@@ -746,7 +749,7 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         pl.one = one;
         tr.begin();
         e = launch_contig(pl, tb, s);
-        tr.end(pass_label("contig", p.field, pl.lgr, pl.mode, which));
+        if (tr.on) tr.end(pass_label("contig", p.field, pl.lgr, pl.mode, which));
         if (e != hipSuccess) return e;
     }
     if (ph == PH_SEED_ONLY || ph == PH_FWD_BOTH) return hipSuccess;
@@ -755,7 +758,7 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
     // a single job's own out_len is honoured as well.
     const uint64_t max_out = one ? std::max<uint64_t>(max_m, one->out_len) : max_m;
     uint64_t out_rows = 0;
-    std::vector<uint64_t> mp(p.nlev);
+    uint64_t mp[4] = {0, 0, 0, 0};  // the block size M before level i (nlev <= 4)
     uint64_t M = L;
     for (int i = 0; i < p.nlev; ++i) {
         mp[i] = M;
@@ -780,17 +783,17 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         pl.one = one;
         tr.begin();
         e = launch_strided(pl, tb, s);
-        tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, fused));
+        if (tr.on) tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, fused));
         if (e != hipSuccess) return e;
     }
     tr.begin();
     e = launch_ptrans(p.field, uint64_t(1) << p.lgr[0], L >> p.lgr[0], out_rows, njobs, jobs_dev, one, s);
-    tr.end("ptrans");
+    if (tr.on) tr.end("ptrans");
     if (e != hipSuccess) return e;
     if (any_degen && (e = launch_degen(njobs, jobs_dev, one, s)) != hipSuccess) return e;
     tr.begin();
     e = launch_pack(njobs, words(max_m), jobs_dev, one, s);
-    tr.end("pack");
+    if (tr.on) tr.end("pack");
     return e;
 }
 
@@ -948,7 +951,30 @@ int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint6
 
 namespace {
 void pinned_release_all(ext_ctx *c);
+
+// The address of each device's allocation-free workspace, looked up once per
+// device (with that device current) and kept for the life of the process.
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch;
+
+hipError_t scratch_for_device(int device, void **out) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch.find(device);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    const hipError_t e = noalloc_scratch_address(&p);  // the caller made `device` current
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    }
+    g_scratch[device] = p;
+    *out = p;
+    return hipSuccess;
 }
+}  // namespace
 
 // ================================================================== C-ABI
 
@@ -965,6 +991,7 @@ const char *ext_strerror(int code) {
         case EXT_ENOMEM: return "workspace exceeds the context's HBM budget";
         case EXT_ETOOLARGE: return "transform length would exceed 2^32";
         case EXT_EDEVICE: return "HIP runtime error";
+        case EXT_ESCRATCH: return "workspace exceeds the allocation-free entry point's fixed scratch";
     }
     return "unknown error code";
 }
@@ -1016,6 +1043,10 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
     if (hipSetDevice(hip_device) != hipSuccess) return EXT_EDEVICE;
     ext_ctx *c = new ext_ctx();
     c->device = hip_device;
+    if (scratch_for_device(hip_device, &c->scratch) != hipSuccess) {
+        delete c;
+        return EXT_EDEVICE;
+    }
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
         delete c;
@@ -1225,6 +1256,39 @@ int extract_dodis(ext_ctx *ctx, const uint64_t *x, const uint64_t *y, uint64_t n
                   uint32_t flags, int32_t *status, void *stream) {
     if (flags & EXT_SEED_LINEAR) return EXT_EINVAL;
     return extract_one(ctx, EXT_KIND_DODIS, x, n, y, m, z, flags, status, (hipStream_t)stream);
+}
+
+int extract_toeplitz_noalloc(ext_ctx *c, const uint64_t *x, uint64_t n, const uint64_t *y, uint64_t m, uint64_t *z,
+                             uint32_t flags, int32_t *status, void *stream) {
+    if (!c || !c->scratch) return EXT_EINVAL;
+    if (flags & ~(EXT_SEED_LINEAR | EXT_SYNC)) return EXT_EINVAL;
+    Shape sh;
+    int rc = shape_of(EXT_KIND_TOEPLITZ, n, m, sh);
+    if (rc) return rc;
+    if ((rc = validate(sh, x, y, z, flags)) != EXT_OK) return rc;
+    Plan p;
+    if ((rc = plan_for(c, sh.Lmin, p)) != EXT_OK) return rc;
+    // the last 256 bytes of the scratch hold the status word of EXT_SYNC calls
+    // without one of their own
+    const size_t status_off = NOALLOC_SCRATCH_BYTES - 256;
+    if (workspace_layout(p).total > status_off) return EXT_ESCRATCH;
+    if (hipSetDevice(c->device) != hipSuccess) return EXT_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)c->scratch;
+    int32_t *st = status;
+    const bool own_status = (flags & EXT_SYNC) && !st;
+    if (own_status) st = (int32_t *)(ws + status_off);
+    JobDev jd = make_jobdev(sh, p, x, y, z, st, flags, p.small ? nullptr : ws);
+    // every workspace region is written before it is read (embedded bits, both
+    // arrays, the parity string), so nothing needs clearing; launches are not
+    // traced (tracing creates events)
+    if (enqueue(c, p, 1, nullptr, &jd, sh.m, false, s, /*capturing=*/true) != hipSuccess) return EXT_EDEVICE;
+    if (!(flags & EXT_SYNC)) return EXT_OK;
+    if (hipStreamSynchronize(s) != hipSuccess) return EXT_EDEVICE;
+    int32_t v = 0;
+    if (hipMemcpy(&v, st, sizeof(v), own_status ? hipMemcpyDeviceToHost : hipMemcpyDefault) != hipSuccess)
+        return EXT_EDEVICE;
+    return v;
 }
 
 int extract_von_neumann(ext_ctx *c, const uint64_t *x, uint64_t n, uint64_t *z, uint64_t z_words, uint64_t *m_out,

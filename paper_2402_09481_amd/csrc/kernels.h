@@ -160,6 +160,14 @@ hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint64_t rows, uint3
 // Dodis degenerate-input check (writes flags).
 hipError_t launch_degen(uint32_t njobs, const JobDev *jobs, const JobDev *one, hipStream_t s);
 
+// Fixed device workspace of the allocation-free Toeplitz entry point: one array
+// per GPU for the life of the process (ntt.hip). noalloc_scratch_address looks
+// up the calling thread's current device's copy (hipGetSymbolAddress) and must
+// be called with that device current; kernels take the returned address, never
+// the array's host-side name.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(40) << 20;  // = EXT_NOALLOC_SCRATCH_BYTES
+hipError_t noalloc_scratch_address(void **ptr);
+
 // Von Neumann compaction (vonneumann.hip). Workspace of one call: the
 // look-back state of every tile (flag in bits 62-63, value below), the partial
 // first and last output word of every tile, counter[0] = tile ticket,

@@ -962,6 +962,17 @@ __global__ void __launch_bounds__(1024) k_small_persist(const JobDev *jobs, Smal
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
 
+// The allocation-free entry point's workspace: one copy on every GPU the library
+// runs on, for the life of the process. Host code uses the address that
+// noalloc_scratch_address returns, never this name (on the host it is only a
+// stand-in for the symbol).
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch_address(void **ptr) {
+    *ptr = nullptr;
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
 // ------------------------------------------------------------------ pack, degenerate check
 
 __global__ void __launch_bounds__(256) k_pack(const JobDev *jobs, JobDev one) {
