@@ -494,7 +494,11 @@ def cpu_baseline_batched(jobs, zs, blocks=128, seed=5):
 
 
 def run_paper_shapes(log, reps=2):
-    """The paper's QKD privacy-amplification shapes (NEXT row f3)."""
+    """The paper's QKD privacy-amplification shapes and QRNG randomness-extraction
+    shapes (NEXT row f3): QKD as two pieces of 2^30 over 3*2^30+1, QRNG (n = 6.5e9)
+    as the piece schedule over the 64-bit field with transforms of 2^31."""
+    import ctypes
+
     import numpy as np
     import torch
 
@@ -502,24 +506,46 @@ def run_paper_shapes(log, reps=2):
     import workloads as W
     out = {}
     ctx = P.Context(0)
-    for name, make in (("qkd_toeplitz", W.qkd_toeplitz), ("qkd_circulant", lambda: W.qkd_circulant(P.next_na_set))):
+
+    def host_job(make):
+        def f():
+            job = make()
+            return (job.kind, job.n, job.m, torch.from_numpy(job.x.view(np.int64)).cuda(),
+                    torch.from_numpy(job.y.view(np.int64)).cuda())
+        return f
+
+    def qrng_t():
+        n, m, x, y = W.qrng_toeplitz_device()
+        return "toeplitz", n, m, x, y
+
+    def qrng_c():
+        n, m, x, y = W.qrng_circulant_device(P.closest_na_set)
+        return "circulant", n, m, x, y
+
+    shapes = (("qkd_toeplitz", host_job(W.qkd_toeplitz)),
+              ("qkd_circulant", host_job(lambda: W.qkd_circulant(P.next_na_set))),
+              ("qrng_toeplitz", qrng_t), ("qrng_circulant", qrng_c))
+    for name, make in shapes:
         log("paper shapes: %s" % name)
-        job = make()
-        x = torch.from_numpy(job.x.view(np.int64)).cuda()
-        y = torch.from_numpy(job.y.view(np.int64)).cuda()
-        z = torch.empty(P.words(job.m), dtype=torch.int64, device="cuda")
-        ctx.extract(job.kind, x, y, job.n, job.m, z=z, sync=True)
+        kind, n, m, x, y = make()
+        z = torch.empty(P.words(m), dtype=torch.int64, device="cuda")
+        ctx.extract(kind, x, y, n, m, z=z, sync=True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            ctx.extract(job.kind, x, y, job.n, job.m, z=z)
+            ctx.extract(kind, x, y, n, m, z=z)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        out[name] = {"kind": job.kind, "n": job.n, "m": job.m, "ms": round(ms, 3),
-                     "output_Mbit_s": round(job.m / (ms * 1e-3) / 1e6, 2),
-                     "input_Mbit_s": round(job.n / (ms * 1e-3) / 1e6, 2)}
+        wb = ctypes.c_int32()
+        L = int(ctx._lib.ext_plan_length(P.KINDS[kind], n, m, ctypes.byref(wb)))
+        out[name] = {"kind": kind, "n": n, "m": m, "ms": round(ms, 3),
+                     "output_Mbit_s": round(m / (ms * 1e-3) / 1e6, 2),
+                     "input_Mbit_s": round(n / (ms * 1e-3) / 1e6, 2),
+                     "transform_length": L, "word_bits": wb.value}
         del x, y, z
+        ctx.trim()
+        torch.cuda.empty_cache()
     ctx.close()
     torch.cuda.empty_cache()
     return out

@@ -86,7 +86,14 @@ extern "C" {
  * over the reversed input) split at a = ceil(n/2) rounded up to whole words,
  * each part extracted with its own seed window, the two products added in the
  * transform domain before one inverse — same bits, 32-bit arithmetic. This flag
- * keeps the one transform of nextpow2(n+m-1) over 2^64 - 2^32 + 1. */
+ * keeps the one transform of nextpow2(n+m-1) over 2^64 - 2^32 + 1.
+ * Shapes longer than one transform of 2^32 (n + m - 1 > 2^32, such as the
+ * paper's QRNG example with n = 6.5e9) always run as k pieces over the 64-bit
+ * field: the same split into k balanced, word-aligned pieces of input positions,
+ * each piece's transforms of 2^31 (2^32 when m leaves pieces under 2^29), the k
+ * products summed in the transform domain (every coefficient of the whole sum is
+ * at most n < 2^64 - 2^32 + 1) before one inverse. Four arrays of transform
+ * length words; m must be at most 2^32 - 64. */
 #define EXT_SINGLE_TRANSFORM 16u
 
 typedef struct ext_ctx ext_ctx;

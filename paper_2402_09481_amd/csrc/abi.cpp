@@ -185,8 +185,8 @@ struct Plan {
     bool small = false;
     int nlev = 0;
     int lgr[4] = {0, 0, 0, 0};
-    int pieces = 1;      // 2: the two-piece schedule (Toeplitz input split at `split` bits)
-    uint64_t split = 0;
+    int pieces = 1;      // >= 2: a piece schedule, the defining sum split over input
+    uint64_t split = 0;  // positions in pieces of `split` bits (a multiple of 64)
 };
 
 constexpr int MIN_LEVEL_LG = 7;
@@ -266,7 +266,7 @@ Layout workspace_layout(const Plan &p) {
     l.a = 0;
     l.b = arr;
     size_t off = 2 * arr;
-    if (p.pieces == 2) {
+    if (p.pieces >= 2) {
         l.a2 = off;
         l.b2 = off + arr;
         off += 2 * arr;
@@ -317,7 +317,9 @@ int shape_of(int kind, uint64_t n, uint64_t m, Shape &s) {
     } else {
         return EXT_EINVAL;
     }
-    if (s.Lmin > (uint64_t(1) << 32)) return EXT_ETOOLARGE;
+    // beyond one transform of 2^32 the single calls run a piece schedule over the
+    // 64-bit field (plan_shape); m itself must leave room in a transform of 2^32
+    if (s.m > (uint64_t(1) << 32) - 64) return EXT_ETOOLARGE;
     return EXT_OK;
 }
 
@@ -333,6 +335,9 @@ bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
 }
 
 uint64_t words(uint64_t bits) { return (bits + 63) >> 6; }
+
+// the length of the sum over j: Toeplitz and Dodis n, Circulant n_in + 1
+uint64_t conv_n(const Shape &s) { return s.kind == EXT_KIND_CIRCULANT ? s.n + 1 : s.n; }
 
 uint64_t seed_bits(const Shape &s) {
     if (s.kind == EXT_KIND_TOEPLITZ) return s.n + s.m - 1;
@@ -361,21 +366,23 @@ uint64_t pointwise_K(const Plan &p) {
     return FGL::powmod(FGL::powmod(2, p.lg), FGL::P - 2);
 }
 
-// piece: 0 for a single transform and for the first piece of the two-piece
-// schedule (which also points at the second piece's product), 1 for its second.
+// piece: 0 for a single transform; for a piece schedule, the piece (0 .. pieces-1).
+// Piece q takes the input positions [q a, min((q+1) a, n)) of the defining sum
+// (a = p.split) and runs on array pair q mod 2; its product spectrum goes to its
+// B array, and S2 of piece q points at piece q+1's B (the sum of the later pieces'
+// products, which its last pass adds).
 JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint64_t *y, uint64_t *z, int32_t *status,
                    uint32_t flags, char *ws, int piece = 0) {
     JobDev j;
     std::memset(&j, 0, sizeof(j));
     const Layout l = workspace_layout(p);
+    const bool odd = (piece & 1) != 0;
     if (ws) {
-        j.A = ws + (piece ? l.a2 : l.a);
-        j.B = ws + (piece ? l.b2 : l.b);
+        j.A = ws + (odd ? l.a2 : l.a);
+        j.B = ws + (odd ? l.b2 : l.b);
         j.pb = (uint64_t *)(ws + l.pb);
         j.S = j.A;
-        if (p.pieces == 2 && piece == 0) {
-            j.S2 = ws + l.b2;  // the second piece's product spectrum (C_PROD)
-        }
+        if (p.pieces >= 2 && piece + 1 < p.pieces) j.S2 = ws + (odd ? l.b : l.b2);
         j.eb[0] = (uint64_t *)(ws + l.eb0);
         j.eb[1] = (uint64_t *)(ws + l.eb1);
         j.flags = (uint32_t *)(ws + l.flags);
@@ -387,33 +394,34 @@ JobDev make_jobdev(const Shape &s, const Plan &p, const uint64_t *x, const uint6
     j.nfold = s.nfold;
     j.out_len = s.out_len;
     j.K = pointwise_K(p);
-    if (s.kind == EXT_KIND_TOEPLITZ && p.pieces == 2) {
-        // z_i = sum_j s_{i-j+n-1} x_j split at j = a: piece 0 is the Toeplitz
-        // extractor of x_0..x_{a-1} with the seed window s_{n-a} .., piece 1 that of
-        // x_a..x_{n-1} with the window s_0 .. (each window a_p + m - 1 bits long)
-        const uint64_t N = s.n + s.m - 1, a = p.split;
-        const uint64_t ap = piece ? s.n - a : a, off = piece ? 0 : s.n - a, Np = ap + s.m - 1;
-        const uint64_t rot = ((flags & EXT_SEED_LINEAR) ? off : off + s.m) % N;
-        j.ex = Emb{piece ? x + a / 64 : x, ap, 0, 0, 0, 0, EMB_PREFIX, 0};
-        j.ey = Emb{y, Np, ap - 1, Np, rot, N, EMB_SEED, 0};
-        j.degen_n = 0;
+    if (p.pieces >= 2) {
+        // z_i = sum_j s_(i-j+n-1) x'_j (Toeplitz: x' = x, s the seed in the linear
+        // order; Dodis and Circulant: x' = rev of the circulant generator, s_k =
+        // y_(k mod n)). The share of positions [j0, j0 + w) is the Toeplitz extraction
+        // of x'_j0 .. x'_(j0+w-1) with the seed window s_t0 .. s_(t0+w+m-2),
+        // t0 = n - j0 - w (each index i - j + n - 1 = t0 + (w - 1 + i - (j - j0))).
+        const uint64_t n = conv_n(s), a = p.split;
+        const uint64_t j0 = (uint64_t)piece * a, w = std::min<uint64_t>(a, n - j0), t0 = n - j0 - w;
+        const uint64_t Np = w + s.m - 1;
+        if (s.kind == EXT_KIND_TOEPLITZ) {
+            const uint64_t N = s.n + s.m - 1;
+            const uint64_t rot = ((flags & EXT_SEED_LINEAR) ? t0 : t0 + s.m) % N;  // s_k = y_((k+m) mod N)
+            j.ex = Emb{x + j0 / 64, w, 0, 0, 0, 0, EMB_PREFIX, 0};
+            j.ey = Emb{y, Np, w - 1, Np, rot, N, EMB_SEED, 0};
+            j.degen_n = 0;
+        } else {
+            // x'_(j0+i) = generator bit n-1-j0-i: the reversed embedding of the
+            // generator's first n - j0 positions, w of them
+            j.ex = Emb{x, s.n, w, n - j0, 0, 0, EMB_REV, 0};
+            j.ey = Emb{y, n, w - 1, Np, t0 % n, n, EMB_SEED, 0};
+            j.degen_n = (s.kind == EXT_KIND_DODIS && piece == 0) ? s.n : 0;
+        }
     } else if (s.kind == EXT_KIND_TOEPLITZ) {
         const uint64_t N = s.n + s.m - 1;
         j.ex = Emb{x, s.n, 0, 0, 0, 0, EMB_PREFIX, 0};
         const uint64_t rot = (flags & EXT_SEED_LINEAR) ? 0 : (s.m % N);
         j.ey = Emb{y, N, s.n - 1, N, rot, N, EMB_SEED, 0};
         j.degen_n = 0;
-    } else if (p.pieces == 2) {
-        // Dodis/Circulant as the linear-order Toeplitz extractor of rev(x') with the
-        // periodic seed s_k = y_(k mod n), split at j = a like the Toeplitz shapes:
-        // piece 0 takes rev(x')_0..a-1 = x'_(n-1)..x'_(n-a) with the seed window
-        // s_(n-a).., piece 1 rev(x')_a..n-1 = x'_(n-a-1)..x'_0 with the window s_0..
-        const uint64_t n = s.kind == EXT_KIND_CIRCULANT ? s.n + 1 : s.n;
-        const uint64_t a = p.split;
-        const uint64_t ap = piece ? n - a : a, off = piece ? 0 : n - a, Np = ap + s.m - 1;
-        j.ex = piece ? Emb{x, s.n, n - a, n - a, 0, 0, EMB_REV, 0} : Emb{x, s.n, a, n, 0, 0, EMB_REV, 0};
-        j.ey = Emb{y, n, ap - 1, Np, off % n, n, EMB_SEED, 0};
-        j.degen_n = (s.kind == EXT_KIND_DODIS && piece == 0) ? s.n : 0;
     } else {
         // circulant length n (Circulant: n_in + 1 with x' = [x, 0]); x reversed, the
         // seed repeated with period n, output z_i = XOR_j s_{i-j+n-1} rev(x')_j
@@ -448,6 +456,7 @@ struct ext_ctx {
     Tables tb[NFIELDS];
     void *tb_mem[NFIELDS][3] = {};
     int force_field = 0;
+    uint64_t piece_bits = 0;  // testing aid: piece schedule for every sum longer than this
     void *scratch = nullptr;  // this device's allocation-free workspace (noalloc_scratch_address)
     std::map<int, Plan> tuned;  // key: field * 64 + lg
     hipStream_t capture_stream = nullptr;
@@ -512,14 +521,16 @@ bool valid_plan(const Plan &p) {
 // The built-in plan, or the context's tuned one for the same field and length
 // (also in a context that forces a field: a tuned plan of that field applies, so
 // that every plan of every field can be run and checked).
-int plan_for(ext_ctx *c, uint64_t Lmin, Plan &p) {
-    int rc = make_plan(Lmin, c ? c->force_field : 0, p);
+int plan_in_field(ext_ctx *c, uint64_t Lmin, int force, Plan &p) {
+    int rc = make_plan(Lmin, force, p);
     if (rc != EXT_OK || !c) return rc;
     std::lock_guard<std::mutex> g(c->mu);
     auto it = c->tuned.find(p.field * 64 + p.lg);
     if (it != c->tuned.end()) p = it->second;
     return EXT_OK;
 }
+
+int plan_for(ext_ctx *c, uint64_t Lmin, Plan &p) { return plan_in_field(c, Lmin, c ? c->force_field : 0, p); }
 
 // Two-piece schedule for shapes beyond one transform of 3*2^30+1. The extraction
 // is a sum over input positions j (Toeplitz: z_i = sum_j s_(i-j+n-1) x_j; Dodis and
@@ -532,17 +543,47 @@ int plan_for(ext_ctx *c, uint64_t Lmin, Plan &p) {
 // inverse.
 constexpr uint64_t TWO_PIECE_MIN_N = 128;
 uint64_t two_piece_split(uint64_t n) { return ((n + 1) / 2 + 63) & ~uint64_t(63); }
-// the length of the sum over j: Toeplitz and Dodis n, Circulant n_in + 1
-uint64_t conv_n(const Shape &s) { return s.kind == EXT_KIND_CIRCULANT ? s.n + 1 : s.n; }
 
 // The plan for a shape: a single transform (plan_for), or the two-piece
 // schedule for a shape whose single transform would need the 64-bit field while
 // each piece fits 3*2^30+1 (unless the caller asks for one transform).
 // Forced-field contexts keep single transforms, except force 4 (testing aid: two
 // pieces whenever n allows).
+// Piece schedule over the 64-bit field, for shapes beyond one transform of 2^32
+// (or, as a testing aid, any shape whose sum is longer than the context's
+// piece_bits): the sum over input positions in k balanced pieces of a bits
+// (a multiple of 64), each piece a Toeplitz extraction run as transforms of
+// nextpow2(a + m - 1) <= 2^32 (2^31 unless the output leaves pieces under 2^29),
+// the k products added in the transform domain (every coefficient of the whole
+// sum is at most n < 2^64 - 2^32 + 1) before one inverse.
+int plan_pieces_gl(ext_ctx *c, const Shape &s, uint64_t forced_bits, Plan &p) {
+    const uint64_t n = conv_n(s);
+    uint64_t a;
+    if (forced_bits) {
+        a = (forced_bits + 63) & ~uint64_t(63);
+    } else {
+        const int lg = (uint64_t(1) << 31) >= s.m + (uint64_t(1) << 29) ? 31 : 32;
+        const uint64_t amax = ((uint64_t(1) << lg) - s.m + 1) & ~uint64_t(63);
+        if (amax < 64) return EXT_ETOOLARGE;
+        const uint64_t k = (n + amax - 1) / amax;
+        a = (((n + k - 1) / k) + 63) & ~uint64_t(63);
+    }
+    const int rc = plan_in_field(c, a + s.m - 1, 2, p);
+    if (rc != EXT_OK) return rc;
+    p.split = a;
+    p.pieces = (int)((n + a - 1) / a);
+    if (p.pieces < 2) {
+        p.pieces = 1;
+        p.split = 0;
+    }
+    return EXT_OK;
+}
+
 int plan_shape(ext_ctx *c, const Shape &s, Plan &p, uint32_t flags = 0) {
     const int force = c ? c->force_field : 0;
     const uint64_t n = conv_n(s);
+    const uint64_t piece_bits = c ? c->piece_bits : 0;
+    if (s.Lmin > (uint64_t(1) << 32) || (piece_bits && n > piece_bits)) return plan_pieces_gl(c, s, piece_bits, p);
     const bool can_split = !(flags & EXT_SINGLE_TRANSFORM) && n >= TWO_PIECE_MIN_N &&
                            two_piece_split(n) + s.m - 1 <= (uint64_t(1) << FP0::LGMAX);
     if (force == 4) {
@@ -686,7 +727,7 @@ std::string pass_label(const char *what, int field, int lgr, int mode, int which
 // transforms, the seed's last level multiplied by the input's spectrum (the
 // piece's product, left in B); TWO: the first piece, whose fused pass adds the
 // second piece's product.
-enum Phase { PH_COLD = 0, PH_SEED_ONLY = 1, PH_WARM = 2, PH_FWD_BOTH = 3, PH_TWO = 4 };
+enum Phase { PH_COLD = 0, PH_SEED_ONLY = 1, PH_WARM = 2, PH_FWD_BOTH = 3, PH_TWO = 4, PH_FWD_ACC = 5 };
 
 hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs_dev, const JobDev *one,
                    uint64_t max_m, bool any_degen, hipStream_t s, bool capturing = false, Phase ph = PH_COLD) {
@@ -734,11 +775,12 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         PassLaunch pl;
         pl.field = p.field;
         pl.lgr = lc;
-        pl.mode = (ph == PH_FWD_BOTH && which == 1)
-                      ? C_PROD
-                      : (ph == PH_SEED_ONLY || ph == PH_FWD_BOTH || ((ph == PH_COLD || ph == PH_TWO) && which == 0))
-                            ? C_FWD
-                            : ph == PH_TWO ? C_FUSED2 : C_FUSED;
+        const bool fwd_only = ph == PH_SEED_ONLY || ph == PH_FWD_BOTH || ph == PH_FWD_ACC;
+        pl.mode = (ph == PH_FWD_BOTH && which == 1)   ? C_PROD
+                  : (ph == PH_FWD_ACC && which == 1)  ? C_PROD_ADD
+                  : (fwd_only || ((ph == PH_COLD || ph == PH_TWO) && which == 0)) ? C_FWD
+                  : ph == PH_TWO                      ? C_FUSED2
+                                                      : C_FUSED;
         pl.which = which;
         pl.S = 0;
         pl.Mprev = 0;
@@ -752,7 +794,7 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         if (tr.on) tr.end(pass_label("contig", p.field, pl.lgr, pl.mode, which));
         if (e != hipSuccess) return e;
     }
-    if (ph == PH_SEED_ONLY || ph == PH_FWD_BOTH) return hipSuccess;
+    if (ph == PH_SEED_ONLY || ph == PH_FWD_BOTH || ph == PH_FWD_ACC) return hipSuccess;
     // inverse: strided levels backwards; level 0 writes packed parity. The output
     // length out_len is m for every shape built here (batch descriptors included);
     // a single job's own out_len is honoured as well.
@@ -921,9 +963,14 @@ int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint6
             if (e == hipSuccess) e = hipEventRecord(se->used, s);
             std::lock_guard<std::mutex> g(c->mu);
             se->busy--;
-        } else if (p.pieces == 2) {
-            const JobDev jd1 = make_jobdev(sh, p, x, y, z, st, flags, lease.ptr, 1);
-            e = enqueue(c, p, 1, nullptr, &jd1, sh.m, false, s, false, PH_FWD_BOTH);
+        } else if (p.pieces >= 2) {
+            // the last piece's product, then each earlier piece's product plus the sum
+            // so far, then the first piece fused with that sum, one inverse, parity
+            for (int q = p.pieces - 1; q >= 1 && e == hipSuccess; --q) {
+                const JobDev jq = make_jobdev(sh, p, x, y, z, st, flags, lease.ptr, q);
+                e = enqueue(c, p, 1, nullptr, &jq, sh.m, false, s, false,
+                            q == p.pieces - 1 ? PH_FWD_BOTH : PH_FWD_ACC);
+            }
             if (e == hipSuccess) e = enqueue(c, p, 1, nullptr, &jd, sh.m, jd.degen_n != 0, s, false, PH_TWO);
         } else {
             e = enqueue(c, p, 1, nullptr, &jd, sh.m, jd.degen_n != 0, s);
@@ -1058,6 +1105,8 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
     if (ff && !strcmp(ff, "bb")) c->force_field = 1;
     if (ff && !strcmp(ff, "p0")) c->force_field = 3;
     if (ff && !strcmp(ff, "p0x2")) c->force_field = 4;  // two-piece schedule wherever it can run
+    // testing aid: the 64-bit piece schedule with pieces of this many input bits
+    if (const char *pb = getenv("EXT_PIECE_BITS")) c->piece_bits = strtoull(pb, nullptr, 10);
     // twiddle tables
     auto upload = [&](int f, int k, const void *src, size_t bytes) -> bool {
         void *d = nullptr;

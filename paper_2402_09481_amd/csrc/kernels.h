@@ -114,11 +114,13 @@ constexpr int strided_cols(int word_bits, int mode) {
 // Contiguous pass over rows of R = 2^lgr consecutive words (last level).
 // C_FUSED: the seed's last forward level, the product with the input spectrum S
 // and the first inverse level (the factor L^-1, K, is applied by the last
-// inverse pass, S_INV_PARITY). Two-piece schedule: C_PROD is the second piece's
-// seed last forward level times its input spectrum S, written back (the piece's
-// product spectrum); C_FUSED2 is C_FUSED of the first piece with that product
-// S2 added before the inverse.
-enum ContigMode : int { C_FWD = 0, C_FUSED = 1, C_FUSED2 = 2, C_PROD = 3 };
+// inverse pass, S_INV_PARITY). Piece schedules (the defining sum split over
+// input positions, the pieces' products added in the transform domain): C_PROD
+// is the last piece's seed last forward level times its input spectrum S,
+// written back (the piece's product spectrum); C_PROD_ADD the same plus the
+// product sum S2 of the later pieces; C_FUSED2 is C_FUSED of the first piece
+// with the sum S2 added before the inverse.
+enum ContigMode : int { C_FWD = 0, C_FUSED = 1, C_FUSED2 = 2, C_PROD = 3, C_PROD_ADD = 4 };
 
 struct PassLaunch {
     int field, lgr, mode;

@@ -45,7 +45,7 @@
 #include "field.h"
 #include "kernels.h"
 
-// The file is compiled once per part (NTT_PART = 0..6) so that the template
+// The file is compiled once per part (NTT_PART = 0..7) so that the template
 // instantiations build in parallel; without NTT_PART everything is built.
 #ifndef NTT_PART
 #define NTT_PART -1
@@ -211,7 +211,7 @@ __host__ __device__ constexpr int step_twiddle_words(int lgr, int order, bool st
 // 64-bit row pass 9% faster; the fused row pass 2% slower, so it keeps the
 // global loads.
 __host__ __device__ constexpr bool lds_twiddles(bool strided, int cmode) {
-    return strided || cmode == C_FWD || cmode == C_PROD;
+    return strided || cmode == C_FWD || cmode == C_PROD || cmode == C_PROD_ADD;
 }
 // SMODE: the pass mode (StridedMode for strided tiles, ContigMode otherwise).
 template <class F, int LGR, bool STRIDED, int ORDER = 1, int SMODE = S_FWD_BITS>
@@ -652,10 +652,12 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
     }
     constexpr int RADL = Ends<Tl, false>::RAD_LAST;
     constexpr int GPTL = EPT / RADL;
-    // C_PROD: the spectrum operand's values are loaded before the transform, so
-    // that their latency overlaps it (its registers are free under the LDS limit)
-    T sv[MODE == C_PROD ? EPT : 1];
-    if constexpr (MODE == C_PROD) {
+    // C_PROD, C_PROD_ADD: the spectrum operand's values are loaded before the
+    // transform, so that their latency overlaps it (its registers are free under
+    // the LDS limit)
+    constexpr bool PROD = (MODE == C_PROD || MODE == C_PROD_ADD);
+    T sv[PROD ? EPT : 1];
+    if constexpr (PROD) {
 #pragma unroll
         for (int q = 0; q < GPTL; ++q) {
             int c, j;
@@ -701,6 +703,9 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
                 const uint64_t gi = base + (uint64_t)c * R + j + t * (R / RADL);
                 if constexpr (MODE == C_PROD)
                     gstore(data + gi, F::mont(v[q * RADL + t], sv[q * RADL + t]));
+                else if constexpr (MODE == C_PROD_ADD)
+                    gstore(data + gi, F::add(F::mont(v[q * RADL + t], sv[q * RADL + t]),
+                                             F::as_b(gload((const T *)J.S2 + gi))));
                 else
                     gstore(data + gi, v[q * RADL + t]);
             }
@@ -1094,13 +1099,17 @@ template <class F, int LGR>
 static hipError_t contig_one(const PassLaunch &p, const KArgs &ka, hipStream_t s) {
     using Tl = Tile<F, LGR, false>;
     dim3 grid((unsigned)p.tiles, p.njobs), block(Tl::NT);
-    if (p.mode == C_FUSED2 || p.mode == C_PROD) {
-        // only the 32-bit field 3*2^30+1 runs the two-piece schedule
-        if constexpr (std::is_same<F, FP0>::value) {
+    if (p.mode == C_FUSED2 || p.mode == C_PROD || p.mode == C_PROD_ADD) {
+        // piece schedules: two pieces over 3*2^30+1, any number over the 64-bit field
+        if constexpr (std::is_same<F, FP0>::value || std::is_same<F, FGL>::value) {
             if (p.mode == C_FUSED2)
                 hipLaunchKernelGGL((k_contig<F, LGR, C_FUSED2>), grid, block, 0, s, ka);
-            else
+            else if (p.mode == C_PROD)
                 hipLaunchKernelGGL((k_contig<F, LGR, C_PROD>), grid, block, 0, s, ka);
+            else if constexpr (std::is_same<F, FGL>::value)
+                hipLaunchKernelGGL((k_contig<F, LGR, C_PROD_ADD>), grid, block, 0, s, ka);
+            else
+                return hipErrorInvalidValue;
         } else {
             return hipErrorInvalidValue;
         }
@@ -1120,6 +1129,7 @@ hipError_t launch_strided_gl(const PassLaunch &p, const Tables &t, hipStream_t s
 hipError_t launch_strided_p0(const PassLaunch &p, const Tables &t, hipStream_t s);
 hipError_t launch_contig_bb(const PassLaunch &p, const Tables &t, hipStream_t s);
 hipError_t launch_contig_gl(const PassLaunch &p, const Tables &t, hipStream_t s);
+hipError_t launch_contig_gl_hi(const PassLaunch &p, const Tables &t, hipStream_t s);  // rows of 2^11..2^13
 hipError_t launch_contig_p0(const PassLaunch &p, const Tables &t, hipStream_t s);
 
 #if NTT_HAS(0)
@@ -1167,12 +1177,22 @@ hipError_t launch_contig_bb(const PassLaunch &p, const Tables &t, hipStream_t s)
 
 #if NTT_HAS(3)
 hipError_t launch_contig_gl(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    if (p.lgr >= 11) return launch_contig_gl_hi(p, t, s);
     KArgs ka = make_args(p, t);
     switch (p.lgr) {
         case 7: return contig_one<FGL, 7>(p, ka, s);
         case 8: return contig_one<FGL, 8>(p, ka, s);
         case 9: return contig_one<FGL, 9>(p, ka, s);
         case 10: return contig_one<FGL, 10>(p, ka, s);
+    }
+    return hipErrorInvalidValue;
+}
+#endif
+
+#if NTT_HAS(7)
+hipError_t launch_contig_gl_hi(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    KArgs ka = make_args(p, t);
+    switch (p.lgr) {
         case 11: return contig_one<FGL, 11>(p, ka, s);
         case 12: return contig_one<FGL, 12>(p, ka, s);
         case 13: return contig_one<FGL, 13>(p, ka, s);

@@ -64,14 +64,16 @@ def test_plan_lengths_and_workspace(lib):
     assert 4 * (1 << 30) * 4 <= big < 4 * (1 << 30) * 4 + (1 << 30)
     big = lib.ext_workspace_bytes(2, big_na, 1000)  # one transform: two arrays of 2^32 64-bit words
     assert 2 * (1 << 32) * 8 <= big < 2 * (1 << 32) * 8 + (1 << 31)
+    # beyond one transform of 2^32: the piece schedule over the 64-bit field
+    assert lib.ext_plan_length(0, 1 << 33, 1 << 31, ctypes.byref(wb)) == 1 << 32 and wb.value == 64
     # invalid shapes
-    for kind, n, m in [(0, 10, 0), (0, 10, 11), (1, 10, 11), (2, 5, 6), (7, 10, 5), (0, (1 << 33), 1 << 31)]:
+    for kind, n, m in [(0, 10, 0), (0, 10, 11), (1, 10, 11), (2, 5, 6), (7, 10, 5), (0, (1 << 41), 10)]:
         assert lib.ext_plan_length(kind, n, m, None) == 0
         assert lib.ext_workspace_bytes(kind, n, m) == 0
 
 
 def test_error_strings(lib):
-    for code in range(0, -7, -1):
+    for code in range(0, -8, -1):
         s = lib.ext_strerror(code).decode()
         assert s and "unknown" not in s
     assert "unknown" in lib.ext_strerror(-99).decode()
@@ -94,17 +96,24 @@ def test_null_context_calls(lib):
     assert lib.ext_tune_set(None, 32, 20, 2, None) == -1
 
 
-def test_paper_qrng_shapes_exceed_the_largest_transform(lib):
-    """The QRNG example (n = 6.5e9) needs a transform longer than 2^32 (the 64-bit
-    field's limit): rejected as too large; the QKD Toeplitz and Circulant shapes run
-    as two pieces of 2^30 each."""
+def test_paper_qrng_shapes_run_as_pieces_of_the_64bit_field(lib):
+    """The QRNG example (n = 6.5e9) is longer than one transform of 2^32: it runs as
+    the piece schedule over the 64-bit field, pieces of transforms of 2^31 (four
+    arrays of 2^31 words); the QKD Toeplitz and Circulant shapes run as two pieces
+    of 2^30 each over 3*2^30+1."""
     import workloads as W
-    assert lib.ext_plan_length(0, W.QRNG_N, W.QRNG_M, None) == 0
-    n_adj = oracle.closest_na(W.QRNG_N + 1)
-    assert lib.ext_plan_length(1, n_adj - 1, 500_000_000, None) == 0
+    wb = ctypes.c_int32()
+    assert lib.ext_plan_length(0, W.QRNG_N, W.QRNG_M, ctypes.byref(wb)) == 1 << 31 and wb.value == 64
+    n_in, m = W.qrng_circulant_shape(oracle.closest_na)
+    assert n_in + 1 == 6_500_000_069 and m == 516_294_932
+    assert lib.ext_plan_length(1, n_in, m, ctypes.byref(wb)) == 1 << 31 and wb.value == 64
+    ws = lib.ext_workspace_bytes(0, W.QRNG_N, W.QRNG_M)
+    assert 4 * (1 << 31) * 8 <= ws < 4 * (1 << 31) * 8 + (1 << 30)
     assert lib.ext_plan_length(0, W.QKD_N, W.QKD_M, None) == 1 << 30
     n_in, m = W.qkd_circulant_shape(oracle.next_na)
     assert lib.ext_plan_length(1, n_in, m, None) == 1 << 30
+    # the output alone must leave room in a transform of 2^32
+    assert lib.ext_plan_length(0, 1 << 40, (1 << 32) - 63, None) == 0
 
 
 def test_von_neumann_host_surface(lib):

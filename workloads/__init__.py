@@ -140,8 +140,19 @@ QKD_EPS = 1e-10
 QKD_RATE = 0.99
 
 # The QRNG example (section "Cryptomite for randomness extraction in (Q)RNG"):
+# n = 6.5e9 raw bits of min-entropy k1 = floor(0.08943 n) = 581,295,000, error
+# 1e-10, Toeplitz output m = floor(k1 + 2 log2(eps)) = 581,294,933; the improved
+# variant uses Circulant with the input length adjusted to the prime with
+# primitive root 2 closest to n + 1 (padding with zeros, or cutting and lowering
+# k1) and a weak seed of min-entropy rate 0.99.
 QRNG_N = 6_500_000_000
 QRNG_M = 581_294_933
+QRNG_K1 = 581_295_000
+QRNG_EPS = 1e-10
+QRNG_RATE = 0.99
+# Bias of i.i.d. stand-in bits with the certified min-entropy rate 0.08943:
+# -log2(max(p, 1 - p)) = 0.08943.
+QRNG_P_ONE = 1.0 - 2.0 ** -0.08943
 
 
 def qkd_toeplitz(seed: int = BASE_SEED + 6) -> Job:
@@ -167,6 +178,36 @@ def qkd_circulant(next_na, seed: int = BASE_SEED + 7) -> Job:
     x[: nwords(QKD_N)] = bernoulli_bits(g, QKD_N, 0.5)  # raw key padded with zeros to n_in bits
     y = bernoulli_bits(g, n_in + 1, 0.5)
     return Job("circulant", n_in, m, x, y)
+
+
+def qrng_circulant_shape(closest_na):
+    """(n_in, m) of the improved QRNG extraction; closest_na comes from the caller."""
+    n_adj = int(closest_na(QRNG_N + 1))
+    k1 = QRNG_K1 - max(0, QRNG_N + 1 - n_adj)
+    k2 = QRNG_RATE * n_adj
+    m = int(math.floor(k1 + k2 - n_adj + 2 * math.log2(QRNG_EPS)))
+    return n_adj - 1, m
+
+
+def qrng_toeplitz_device(seed: int = BASE_SEED + 14):
+    """The QRNG Toeplitz shape as device tensors (x: n i.i.d. bits of the certified
+    min-entropy rate, seed: n + m - 1 bits ~ B(1/2)), drawn with torch's seeded
+    generator on the GPU (1.7 GB of bits). Returns (n, m, x, y)."""
+    x = bernoulli_bits_device(QRNG_N, QRNG_P_ONE, seed)
+    y = bernoulli_bits_device(QRNG_N + QRNG_M - 1, 0.5, seed + 1)
+    return QRNG_N, QRNG_M, x, y
+
+
+def qrng_circulant_device(closest_na, seed: int = BASE_SEED + 15):
+    """The improved QRNG Circulant shape as device tensors: x is the raw bits padded
+    with zeros to n_in bits, y the n_in + 1 seed bits. Returns (n_in, m, x, y)."""
+    import torch
+    n_in, m = qrng_circulant_shape(closest_na)
+    raw = bernoulli_bits_device(QRNG_N, QRNG_P_ONE, seed)
+    x = torch.zeros(nwords(n_in), dtype=torch.int64, device=raw.device)
+    x[: raw.numel()] = raw
+    y = bernoulli_bits_device(n_in + 1, 0.5, seed + 1)
+    return n_in, m, x, y
 
 
 def batch_params(count: int = 4096, seed: int = BASE_SEED + 3, next_na=None,
