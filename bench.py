@@ -57,24 +57,26 @@ def kernel_bytes(label: str, L: int, w: int, n: int, N: int, m: int) -> int:
     L, contiguous mode 2 (first piece's fused pass plus that product) reads 3L, writes L;
     strided mode 3
     (last inverse pass): reads L words, writes m parity bits; pack: m bits in, m bits out;
-    embed: both packed inputs in, both L-bit coefficient strings out; ptrans: the parity
-    bits of the m output coefficients in and out."""
+    embed: both packed inputs in, both L-bit coefficient strings out; ptrans(_pack): the
+    parity bits of the m output coefficients in, packed out. Forward strided levels
+    run both operands in one launch (arr=2): twice the bytes."""
     if label.startswith("pack"):
         return 2 * (m // 8)
     if label.startswith("embed"):  # both packed inputs in, two L-bit coefficient strings out
         return (n + N) // 8 + 2 * (L // 8)
-    if label.startswith("ptrans"):  # the parity bits of the m output coefficients, in and out
+    if label.startswith("ptrans"):  # the parity bits of the m output coefficients in, z out
         return 2 * (m // 8)
     kind = label.split("[")[0]
     fields = dict(kv.split("=") for kv in label.split("[")[1].rstrip("]").split(",")[1:])
     mode, arr = int(fields["mode"]), int(fields.get("arr", 0))
     Lw = L * w
     if kind == "strided":
+        # arr=2: both operands in one launch (the forward levels)
         if mode == 0:
-            return Lw + (n if arr == 0 else N) // 8
+            return {0: Lw + n // 8, 1: Lw + N // 8, 2: 2 * Lw + (n + N) // 8}[arr]
         if mode == 3:
             return Lw + m // 8
-        return 2 * Lw
+        return 2 * Lw * (2 if arr == 2 else 1)
     if kind == "contig":  # mode 2: the two-piece fused pass (3 arrays in, 1 out)
         return 4 * Lw if mode == 2 else 3 * Lw if mode in (1, 3) else 2 * Lw
     return 0
@@ -403,7 +405,7 @@ def run_two_piece(ctx, job, x, y, z, stream, args, single_ms):
             "achieved_GBs": round(total_bytes / (ms * 1e-3) / 1e9, 1), "kernels": kernels}
 
 
-def run_batched(log, count=4096, reps=3):
+def run_batched(log, count=4096, reps=3, per_block=True):
     """The batched workload (4096 Toeplitz/Circulant blocks, n log-uniform in
     [2^10, 2^22], m = n/2): extract_batch (one persistent launch for the
     single-workgroup sizes plus grouped multi-pass launches, replayed from a HIP
@@ -440,11 +442,12 @@ def run_batched(log, count=4096, reps=3):
 
     log("batched: warmup")
     ctx.batch(dev, sync=True, graph=True)
-    ctx.batch(dev_u, sync=True, unbatched=True)
+    if per_block:
+        ctx.batch(dev_u, sync=True, unbatched=True)
     log("batched: timed x%d each" % reps)
     t_b = timed(lambda: ctx.batch(dev, stream=stream, graph=True), reps)
-    t_u = timed(lambda: ctx.batch(dev_u, stream=stream, unbatched=True), reps)
-    same = all(torch.equal(a["z"], b["z"]) for a, b in zip(dev, dev_u))
+    t_u = timed(lambda: ctx.batch(dev_u, stream=stream, unbatched=True), reps) if per_block else float("nan")
+    same = all(torch.equal(a["z"], b["z"]) for a, b in zip(dev, dev_u)) if per_block else None
     zs = [d["z"].cpu().numpy().view(np.uint64).copy() for d in dev]
     sum_m = sum(j.m for j in jobs)
     sum_n = sum(j.n for j in jobs)
@@ -456,7 +459,7 @@ def run_batched(log, count=4096, reps=3):
             "batched_ms": round(t_b, 3), "per_block_ms": round(t_u, 3), "speedup": round(t_u / t_b, 2),
             "batched_Mbit_s": round(sum_m / (t_b * 1e-3) / 1e6, 1),
             "per_block_Mbit_s": round(sum_m / (t_u * 1e-3) / 1e6, 1),
-            "outputs_identical": bool(same)}, jobs, zs
+            "outputs_identical": same}, jobs, zs
 
 
 def cpu_baseline_batched(jobs, zs, blocks=128, seed=5):
@@ -679,6 +682,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0 = skip)")
     ap.add_argument("--batched", action="store_true", help="(default) the 4096-block batched comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--batched-reps", type=int, default=3, help="timed repetitions of each batched form")
+    ap.add_argument("--no-per-block", action="store_true",
+                    help="batched: skip the one-call-per-block comparison (for profiling the batched launches)")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="skip the headline and its CPU legs (for profiling the other legs alone)")
     ap.add_argument("--serving", action="store_true",
                     help="the full serving sweep (1k-50k req/s) instead of the default two offered rates")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
@@ -708,29 +716,32 @@ def main():
         log("copy calibration: %d bytes read + %d bytes written per copy kernel" % (nb, nb))
         del src, dst
         torch.cuda.empty_cache()
-    out, job, z_head = run_headline(args)
-    # the CPU leg: the oracle on a bounded sample of the same workload; its rows
-    # also check the timed extraction's first output bits
-    log("cpu baseline (oracle, %.0f s budget)" % max(args.cpu_seconds, 1.0))
-    cb, rows, want = cpu_baseline(job, max(args.cpu_seconds, 1.0))
-    if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cb
-        log("cpu NTT baseline (one thread)")
-        out["cpu_ntt"] = cpu_ntt_baseline()
-    out["oracle_check"] = check_rows(z_head, rows, want)
-    if not out["oracle_check"]["bits_equal"]:
-        print(json.dumps(out), flush=True)
-        log("MISMATCH: the timed extraction's first %d output bits differ from the oracle's rows" % rows)
-        sys.exit(3)
+    if args.no_headline:
+        out = {"metric": METRIC, "note": "headline skipped (--no-headline)"}
+    else:
+        out, job, z_head = run_headline(args)
+        # the CPU leg: the oracle on a bounded sample of the same workload; its rows
+        # also check the timed extraction's first output bits
+        log("cpu baseline (oracle, %.0f s budget)" % max(args.cpu_seconds, 1.0))
+        cb, rows, want = cpu_baseline(job, max(args.cpu_seconds, 1.0))
+        if args.cpu_seconds > 0:
+            out["cpu_baseline"] = cb
+            log("cpu NTT baseline (one thread)")
+            out["cpu_ntt"] = cpu_ntt_baseline()
+        out["oracle_check"] = check_rows(z_head, rows, want)
+        if not out["oracle_check"]["bits_equal"]:
+            print(json.dumps(out), flush=True)
+            log("MISMATCH: the timed extraction's first %d output bits differ from the oracle's rows" % rows)
+            sys.exit(3)
     if not args.no_small:
         out["small_configs"] = run_small_configs(log)
     if not args.no_batched:
-        b, bjobs, bzs = run_batched(log)
+        b, bjobs, bzs = run_batched(log, reps=args.batched_reps, per_block=not args.no_per_block)
         log("batched: cpu leg (oracle rows on sampled blocks)")
         b["cpu_baseline"], b["oracle_check"] = cpu_baseline_batched(bjobs, bzs)
         out["batched"] = b
         del bjobs, bzs
-        if not b["oracle_check"]["bits_equal"] or not b["outputs_identical"]:
+        if not b["oracle_check"]["bits_equal"] or b["outputs_identical"] is False:
             print(json.dumps(out), flush=True)
             log("MISMATCH in the batched workload")
             sys.exit(3)

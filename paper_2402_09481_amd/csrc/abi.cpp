@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "field.h"
@@ -323,9 +324,27 @@ int shape_of(int kind, uint64_t n, uint64_t m, Shape &s) {
     return EXT_OK;
 }
 
+// is_na with a memo of recent answers: a batch or a serving loop checks the same
+// few thousand lengths on every call (Miller-Rabin plus factoring n - 1, a few
+// microseconds each)
+bool is_na_cached(uint64_t n) {
+    static std::mutex mu;
+    static std::unordered_map<uint64_t, bool> memo;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = memo.find(n);
+        if (it != memo.end()) return it->second;
+    }
+    const bool r = is_na(n);
+    std::lock_guard<std::mutex> g(mu);
+    if (memo.size() >= (size_t(1) << 16)) memo.clear();
+    memo[n] = r;
+    return r;
+}
+
 int check_primes(const Shape &s) {
-    if (s.kind == EXT_KIND_CIRCULANT && !is_na(s.n + 1)) return EXT_ENOTNA;
-    if (s.kind == EXT_KIND_DODIS && !is_na(s.n)) return EXT_ENOTNA;
+    if (s.kind == EXT_KIND_CIRCULANT && !is_na_cached(s.n + 1)) return EXT_ENOTNA;
+    if (s.kind == EXT_KIND_DODIS && !is_na_cached(s.n)) return EXT_ENOTNA;
     return EXT_OK;
 }
 
@@ -463,12 +482,20 @@ struct ext_ctx {
     // pinned status words for EXT_SYNC calls without a status pointer
     std::vector<int32_t *> pinned_status;
     // batch graph cache
+    // Descriptors are staged in two pinned buffers used in turn, so that the host
+    // fills one while the copy of the previous replay may still read the other;
+    // done[k] is recorded after the copy from staging k. The device copy desc_dev
+    // is overwritten only after the previous replay has finished (its stream waits
+    // for `replayed`, recorded after each replay, on the device).
     struct GraphEntry {
         hipGraphExec_t exec = nullptr;
         JobDev *desc_dev = nullptr;
-        JobDev *desc_host = nullptr;  // pinned
+        JobDev *desc_host[2] = {nullptr, nullptr};  // pinned
         size_t ndesc = 0;
-        hipEvent_t done = nullptr;
+        hipEvent_t done[2] = {nullptr, nullptr};
+        bool used[2] = {false, false};
+        int next = 0;
+        hipEvent_t replayed = nullptr;
         bool ever = false;
     };
     std::map<std::string, GraphEntry> graphs;
@@ -742,34 +769,39 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
     const uint64_t L = uint64_t(1) << p.lg;
     hipError_t e;
     tr.begin();
-    e = launch_embed(njobs, L, jobs_dev, one, s);
+    e = launch_embed(njobs, L, jobs_dev, one, any_degen, s);
     if (tr.on) tr.end("embed");
     if (e != hipSuccess) return e;
-    // arrays: `fwd` lists the operands transformed here; the fused pass runs on `fused`
+    // the operands transformed here: both (-1), or only the seed (SEED_ONLY) or only
+    // the input (WARM); the fused pass runs on `fused`
+    const int only = ph == PH_SEED_ONLY ? 1 : ph == PH_WARM ? 0 : -1;
     const int fused = ph == PH_WARM ? 0 : 1;
+    // strided forward levels: both operands in one launch per level (blockIdx.z
+    // selects the array; they are independent until the fused pass)
+    uint64_t Mprev = L;
+    for (int i = 0; i + 1 < p.nlev; ++i) {
+        PassLaunch pl;
+        pl.field = p.field;
+        pl.lgr = p.lgr[i];
+        pl.mode = i == 0 ? S_FWD_BITS : S_FWD;
+        const Geometry g = strided_geometry(p.field, p.lgr[i], pl.mode);
+        pl.which = only;
+        pl.Mprev = Mprev;
+        pl.S = Mprev >> p.lgr[i];
+        pl.tiles = (L / Mprev) * (pl.S / g.C);
+        pl.njobs = njobs;
+        pl.jobs = jobs_dev;
+        pl.one = one;
+        tr.begin();
+        e = launch_strided(pl, tb, s);
+        if (tr.on) tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, only < 0 ? 2 : only));
+        if (e != hipSuccess) return e;
+        Mprev = pl.S;
+    }
+    // the last forward level: the input's first (its spectrum is an operand of the
+    // seed's fused pass)
     for (int which = 0; which < 2; ++which) {
-        if (ph == PH_SEED_ONLY && which == 0) continue;
-        if (ph == PH_WARM && which == 1) continue;
-        uint64_t Mprev = L;
-        for (int i = 0; i + 1 < p.nlev; ++i) {
-            PassLaunch pl;
-            pl.field = p.field;
-            pl.lgr = p.lgr[i];
-            pl.mode = i == 0 ? S_FWD_BITS : S_FWD;
-            const Geometry g = strided_geometry(p.field, p.lgr[i], pl.mode);
-            pl.which = which;
-            pl.Mprev = Mprev;
-            pl.S = Mprev >> p.lgr[i];
-            pl.tiles = (L / Mprev) * (pl.S / g.C);
-            pl.njobs = njobs;
-            pl.jobs = jobs_dev;
-            pl.one = one;
-            tr.begin();
-            e = launch_strided(pl, tb, s);
-            if (tr.on) tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, which));
-            if (e != hipSuccess) return e;
-            Mprev = pl.S;
-        }
+        if (only >= 0 && which != only) continue;
         const int lc = p.lgr[p.nlev - 1];
         const Geometry g = contig_geometry(p.field, lc);
         PassLaunch pl;
@@ -828,11 +860,14 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         if (tr.on) tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, fused));
         if (e != hipSuccess) return e;
     }
+    // the parity transpose writes z itself (the degenerate check ran with the
+    // embedding), unless a job folds (z_i = c_i ^ c_(i+n), which reads the packed
+    // parity string): batch descriptors never fold
+    const bool fold = one && one->nfold;
     tr.begin();
-    e = launch_ptrans(p.field, uint64_t(1) << p.lgr[0], L >> p.lgr[0], out_rows, njobs, jobs_dev, one, s);
-    if (tr.on) tr.end("ptrans");
-    if (e != hipSuccess) return e;
-    if (any_degen && (e = launch_degen(njobs, jobs_dev, one, s)) != hipSuccess) return e;
+    e = launch_ptrans(p.field, uint64_t(1) << p.lgr[0], L >> p.lgr[0], out_rows, njobs, jobs_dev, one, !fold, s);
+    if (tr.on) tr.end(fold ? "ptrans" : "ptrans_pack");
+    if (e != hipSuccess || !fold) return e;
     tr.begin();
     e = launch_pack(njobs, words(max_m), jobs_dev, one, s);
     if (tr.on) tr.end("pack");
@@ -998,6 +1033,22 @@ int extract_one(ext_ctx *c, int kind, const uint64_t *x, uint64_t n, const uint6
 
 namespace {
 void pinned_release_all(ext_ctx *c);
+
+void graph_entry_free(ext_ctx::GraphEntry &ge) {
+    if (ge.exec) hipGraphExecDestroy(ge.exec);
+    if (ge.desc_dev) hipFree(ge.desc_dev);
+    for (int k = 0; k < 2; ++k) {
+        if (ge.desc_host[k]) hipHostFree(ge.desc_host[k]);
+        if (ge.done[k]) hipEventDestroy(ge.done[k]);
+    }
+    if (ge.replayed) hipEventDestroy(ge.replayed);
+}
+
+bool graph_entry_idle(ext_ctx::GraphEntry &ge) {
+    for (int k = 0; k < 2; ++k)
+        if (ge.used[k] && hipEventQuery(ge.done[k]) != hipSuccess) return false;
+    return !ge.ever || hipEventQuery(ge.replayed) == hipSuccess;
+}
 
 // The address of each device's allocation-free workspace, looked up once per
 // device (with that device current) and kept for the life of the process.
@@ -1172,12 +1223,7 @@ void ext_destroy(ext_ctx *c) {
         if (b.used) hipEventDestroy(b.ev);
         hipFree(b.ptr);
     }
-    for (auto &kv : c->graphs) {
-        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-        if (kv.second.desc_dev) hipFree(kv.second.desc_dev);
-        if (kv.second.desc_host) hipHostFree(kv.second.desc_host);
-        if (kv.second.done) hipEventDestroy(kv.second.done);
-    }
+    for (auto &kv : c->graphs) graph_entry_free(kv.second);
     for (int f = 0; f < NFIELDS; ++f)
         for (int k = 0; k < 3; ++k)
             if (c->tb_mem[f][k]) hipFree(c->tb_mem[f][k]);
@@ -1693,11 +1739,8 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
             if (c->graphs.size() >= GRAPH_CACHE_MAX && !c->graphs.count(bl.sig)) {
                 // bounded cache: evict an entry whose last replay is done
                 for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
-                    if (!it->second.ever || hipEventQuery(it->second.done) == hipSuccess) {
-                        if (it->second.exec) hipGraphExecDestroy(it->second.exec);
-                        if (it->second.desc_dev) hipFree(it->second.desc_dev);
-                        if (it->second.desc_host) hipHostFree(it->second.desc_host);
-                        if (it->second.done) hipEventDestroy(it->second.done);
+                    if (graph_entry_idle(it->second)) {
+                        graph_entry_free(it->second);
                         c->graphs.erase(it);
                         break;
                     }
@@ -1707,18 +1750,27 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
         }
         if (!ge->desc_dev) {
             ge->ndesc = ndesc;
-            if (hipMalloc((void **)&ge->desc_dev, desc_bytes + 256) != hipSuccess ||
-                hipHostMalloc((void **)&ge->desc_host, desc_bytes, hipHostMallocDefault) != hipSuccess ||
-                hipEventCreateWithFlags(&ge->done, hipEventDisableTiming) != hipSuccess) {
+            bool ok = hipMalloc((void **)&ge->desc_dev, desc_bytes + 256) == hipSuccess &&
+                      hipEventCreateWithFlags(&ge->replayed, hipEventDisableTiming) == hipSuccess;
+            for (int k = 0; k < 2 && ok; ++k)
+                ok = hipHostMalloc((void **)&ge->desc_host[k], desc_bytes, hipHostMallocDefault) == hipSuccess &&
+                     hipEventCreateWithFlags(&ge->done[k], hipEventDisableTiming) == hipSuccess;
+            if (!ok) {
                 pool_release(c, lease, stream);
                 return EXT_EDEVICE;
             }
         }
         uint32_t *counter = (uint32_t *)((char *)ge->desc_dev + desc_bytes);
-        // the staging of this signature may still be read by the previous replay's copy
-        if (ge->ever) hipEventSynchronize(ge->done);
-        fill_descs(bl, jobs, lease.ptr, ge->desc_host);
-        e = hipMemcpyAsync(ge->desc_dev, ge->desc_host, ndesc * sizeof(JobDev), hipMemcpyHostToDevice, stream);
+        // this staging buffer may still be read by the copy of the replay before last
+        const int k = ge->next;
+        ge->next ^= 1;
+        if (ge->used[k]) hipEventSynchronize(ge->done[k]);
+        fill_descs(bl, jobs, lease.ptr, ge->desc_host[k]);
+        if (ge->ever) e = hipStreamWaitEvent(stream, ge->replayed, 0);  // the last replay read desc_dev
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ge->desc_dev, ge->desc_host[k], ndesc * sizeof(JobDev), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipEventRecord(ge->done[k], stream);
+        ge->used[k] = true;
         if (e == hipSuccess && !ge->exec) {
             hipGraph_t graph = nullptr;
             e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
@@ -1730,7 +1782,7 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
             if (e != hipSuccess) ge->exec = nullptr;
         }
         if (e == hipSuccess) e = hipGraphLaunch(ge->exec, stream);
-        hipEventRecord(ge->done, stream);
+        if (e == hipSuccess) e = hipEventRecord(ge->replayed, stream);
         ge->ever = true;
         pool_release(c, lease, stream);
     } else {

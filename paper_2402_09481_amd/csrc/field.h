@@ -159,23 +159,13 @@ struct FGL {
     static constexpr uint64_t WMAX = 5980198667562970375ull;
     static constexpr int WORD_BITS = 64;
 
-    // x + c EPS (mod 2^64) for c in {0, 1}: one 32 x 32 + 64-bit multiply-add. (The
-    // compiler would otherwise select EPS or 0 and add it as a 64-bit value, which
-    // costs a move that clears the addend's high half; the empty asm keeps it from
-    // turning the product back into that select.)
-    __device__ static inline uint64_t add_eps_if(uint64_t x, uint32_t c) {
-#if defined(__HIP_DEVICE_COMPILE__)
-        asm("" : "+v"(c));
-#endif
-        return (uint64_t)c * EPS + x;
-    }
     // representative in [0, P): subtracting P is adding EPS mod 2^64
-    __device__ static inline uint64_t canon(uint64_t a) { return add_eps_if(a, a >= P ? 1u : 0u); }
+    __device__ static inline uint64_t canon(uint64_t a) { return a + (a >= P ? EPS : 0ull); }
     // a + b for any a < 2^64 and b < P: a single wrap past 2^64 (worth EPS) leaves
     // a + b - 2^64 < P, so adding EPS cannot wrap again.
     __device__ static inline uint64_t add(uint64_t a, uint64_t b) {
-        const uint64_t s = a + b;
-        return add_eps_if(s, s < b ? 1u : 0u);
+        uint64_t s = a + b;
+        return s + (s < b ? EPS : 0ull);
     }
     // a - b for any a < 2^64 and b < P, on 32-bit halves so that the borrow of
     // the high half selects the correction: after a borrow a - b + 2^64 > EPS, so
@@ -205,7 +195,9 @@ struct FGL {
         // add that needs c0 as a value (two more instructions); emits no code
         asm("" : "+v"(r1));
 #endif
-        return add_eps_if(((uint64_t)r1 << 32) | r0, c1);
+        const uint32_t s0 = __builtin_addc(r0, c1 ? 0xFFFFFFFFu : 0u, 0u, &k);
+        const uint32_t s1 = __builtin_addc(r1, 0u, k, &k2);
+        return ((uint64_t)s1 << 32) | s0;
     }
     __device__ static inline uint64_t reduce128(uint64_t hi, uint64_t lo) {
         return reduce((uint32_t)(hi >> 32), (uint32_t)hi, lo);
@@ -237,12 +229,12 @@ struct FGL {
             // x 2^s = hi*2^64 + lo with hi < 2^32: lo + hi*EPS
             uint64_t r;
             bool c = __builtin_add_overflow(x << s, (uint64_t)(uint32_t)(x >> (64 - s)) * EPS, &r);
-            return add_eps_if(r, c ? 1u : 0u);  // r < 2^63 after a wrap
+            return r + (c ? EPS : 0ull);  // r < 2^63 after a wrap
         } else if constexpr (s == 32) {
             // x 2^32 = x1*2^64 + x0*2^32: (x0 << 32) + x1*EPS
             uint64_t r;
             bool c = __builtin_add_overflow(x << 32, (uint64_t)(uint32_t)(x >> 32) * EPS, &r);
-            return add_eps_if(r, c ? 1u : 0u);
+            return r + (c ? EPS : 0ull);
         } else if constexpr (s < 64) {
             return reduce128(x >> (64 - s), x << s);
         } else if constexpr (s == 64) {

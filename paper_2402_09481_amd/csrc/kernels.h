@@ -124,7 +124,8 @@ enum ContigMode : int { C_FWD = 0, C_FUSED = 1, C_FUSED2 = 2, C_PROD = 3, C_PROD
 
 struct PassLaunch {
     int field, lgr, mode;
-    int which;            // 0: array A, 1: array B (ignored by C_FUSED, which reads A and B)
+    int which;            // 0: array A, 1: array B (ignored by C_FUSED, which reads A and B); strided
+                          // passes also -1: both arrays in one launch (blockIdx.z selects)
     uint64_t S, Mprev;    // strided only
     uint64_t tiles;       // workgroups per job
     uint64_t out_rows = 0;  // S_INV_PARITY: rows of the level-0 column transform that hold
@@ -153,12 +154,16 @@ hipError_t launch_small_batch(const SmallClasses &cls, const JobDev *jobs, uint3
                               const Tables &t, hipStream_t s);
 // Packed parity -> z (fold, mask, degenerate check result, status).
 hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, const JobDev *one, hipStream_t s);
-// Lay out both inputs as L-bit coefficient strings (eb[0], eb[1]).
-hipError_t launch_embed(uint32_t njobs, uint64_t max_L, const JobDev *jobs, const JobDev *one, hipStream_t s);
-// Tile-major parity units of the last inverse pass -> packed natural order (pb),
-// rows [0, rows) of R (the rows that hold needed coefficients).
+// Lay out both inputs as L-bit coefficient strings (eb[0], eb[1]); with degen, also
+// the Dodis degenerate-input check (flags).
+hipError_t launch_embed(uint32_t njobs, uint64_t max_L, const JobDev *jobs, const JobDev *one, bool degen,
+                        hipStream_t s);
+// Tile-major parity units of the last inverse pass -> packed natural order, rows
+// [0, rows) of R (the rows that hold needed coefficients): into pb, or with pack
+// straight into z (tail bits cleared, degenerate check applied, status written;
+// shapes without the wrap-around fold).
 hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint64_t rows, uint32_t njobs, const JobDev *jobs,
-                         const JobDev *one, hipStream_t s);
+                         const JobDev *one, bool pack, hipStream_t s);
 // Dodis degenerate-input check (writes flags).
 hipError_t launch_degen(uint32_t njobs, const JobDev *jobs, const JobDev *one, hipStream_t s);
 

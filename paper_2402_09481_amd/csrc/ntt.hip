@@ -431,7 +431,7 @@ struct KArgs {
     JobDev one;
     Tables tb;
     uint64_t S, Mprev;
-    int which;  // array read and written (0: A, 1: B)
+    int which;  // array read and written (0: A, 1: B; -1: both, A for blockIdx.z = 0, B for 1)
 };
 
 // A strided pass: one workgroup per tile of C adjacent columns of R rows. The
@@ -461,7 +461,8 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
     __shared__ T lut[LUT ? 64 : 1];
 
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
-    T *data = (T *)(a.which ? J.B : J.A);
+    const int which = a.which < 0 ? (int)blockIdx.z : a.which;
+    T *data = (T *)(which ? J.B : J.A);
     const T *thi = (const T *)a.tb.hi, *tlo = (const T *)a.tb.lo;
     const uint64_t colTiles = a.S / C;
     // (measured: the remap helps the value passes and slows the bit-reading first
@@ -528,7 +529,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
                 // a row segment of the tile is C adjacent bits starting at a
                 // multiple of C: one C-bit unit, the same address for every
                 // lane of the row
-                const Unit *ub = (const Unit *)J.eb[a.which];
+                const Unit *ub = (const Unit *)J.eb[which];
                 const uint32_t bit = (uint32_t)(gload(ub + (gi - c) / C) >> c) & 1u;
                 if constexpr (LUT) bt[q * RF + t] = bit;
                 x = F::from_bit(bit);
@@ -909,8 +910,36 @@ __host__ __device__ inline uint64_t embed_word(const Emb &e, uint64_t L, uint64_
     return out;
 }
 
+// Dodis degenerate-input check of one job by one 256-thread workgroup: flags[0] =
+// x has a one bit, flags[1] = x has a zero bit (among its first degen_n bits).
+__device__ inline void degen_body(const JobDev &J) {
+    __shared__ uint32_t red[2];
+    if (threadIdx.x < 2) red[threadIdx.x] = 0;
+    __syncthreads();
+    if (J.degen_n) {
+        const uint64_t nw = (J.degen_n + 63) >> 6;
+        uint32_t one_ = 0, zero_ = 0;
+        for (uint64_t w = threadIdx.x; w < nw; w += 256) {
+            uint64_t x = J.ex.bits[w];
+            uint64_t mk = (w + 1 < nw || (J.degen_n & 63) == 0) ? ~0ull : ((1ull << (J.degen_n & 63)) - 1);
+            one_ |= (x & mk) != 0;
+            zero_ |= (~x & mk) != 0;
+        }
+        if (one_) atomicOr(&red[0], 1u);
+        if (zero_) atomicOr(&red[1], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) J.flags[threadIdx.x] = red[threadIdx.x];
+}
+
+// blockIdx.z = 0, 1: the embedding of x, y; z = 2 (launched for shapes with the
+// degenerate check): the check, by the first workgroup of the slice.
 __global__ void __launch_bounds__(256) k_embed(const JobDev *jobs, JobDev one) {
     const JobDev &J = jobs ? jobs[blockIdx.y] : one;
+    if (blockIdx.z == 2) {
+        if (blockIdx.x == 0) degen_body(J);
+        return;
+    }
     // (the descriptor is read once: the stores could alias it)
     const uint64_t L = J.L, nw = L >> 6;
     const int which = blockIdx.z;
@@ -1002,7 +1031,10 @@ __global__ void __launch_bounds__(256) k_pack(const JobDev *jobs, JobDev one) {
 // Tile-major parity units (unit u of row r at u*R + r, C bits each, in J.eb[0]) to
 // packed natural order in J.pb (bit r*S + u*C + c). 64 x 64 units per workgroup
 // through LDS, coalesced on both sides.
-template <int C>
+// PACK: write z itself (the job's first ceil(m/64) words, bits past m cleared,
+// zero for a degenerate Dodis input, and the status word) instead of pb, for
+// shapes without the wrap-around fold; k_pack is then not needed.
+template <int C, bool PACK>
 __global__ void __launch_bounds__(256) k_ptrans(const JobDev *jobs, JobDev one, uint64_t R, uint64_t S) {
     using Unit = UnitOf<C>;
     constexpr int UPW = 64 / C;  // units per word
@@ -1018,6 +1050,8 @@ __global__ void __launch_bounds__(256) k_ptrans(const JobDev *jobs, JobDev one, 
     }
     __syncthreads();
     constexpr int WPR = 64 / UPW;  // words per tile row
+    const uint64_t nwm = (J.m + 63) >> 6;
+    const bool degen = PACK && J.degen_n && (J.flags[0] == 0 || J.flags[1] == 0);
     for (int idx = threadIdx.x; idx < 64 * WPR; idx += 256) {
         const int rr = idx / WPR, wk = idx % WPR;
         const uint64_t r = r0 + rr, u = u0 + (uint64_t)wk * UPW;
@@ -1025,30 +1059,24 @@ __global__ void __launch_bounds__(256) k_ptrans(const JobDev *jobs, JobDev one, 
             uint64_t word = 0;
 #pragma unroll
             for (int k = 0; k < UPW; ++k) word |= (uint64_t)tl[rr][wk * UPW + k] << (k * C);
-            J.pb[r * (S / 64) + u / UPW] = word;
+            const uint64_t wi = r * (S / 64) + u / UPW;
+            if constexpr (PACK) {
+                if (wi < nwm) {
+                    const uint64_t rem = J.m - wi * 64;
+                    if (rem < 64) word &= (1ull << rem) - 1;
+                    J.z[wi] = degen ? 0ull : word;
+                }
+            } else {
+                J.pb[wi] = word;
+            }
         }
     }
+    if (PACK && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && J.status) *J.status = degen ? -3 : 0;
 }
 
 __global__ void __launch_bounds__(256) k_degen(const JobDev *jobs, JobDev one) {
     const JobDev &J = jobs ? jobs[blockIdx.x] : one;
-    __shared__ uint32_t red[2];
-    if (threadIdx.x < 2) red[threadIdx.x] = 0;
-    __syncthreads();
-    if (J.degen_n) {
-        const uint64_t nw = (J.degen_n + 63) >> 6;
-        uint32_t one_ = 0, zero_ = 0;
-        for (uint64_t w = threadIdx.x; w < nw; w += 256) {
-            uint64_t x = J.ex.bits[w];
-            uint64_t mk = (w + 1 < nw || (J.degen_n & 63) == 0) ? ~0ull : ((1ull << (J.degen_n & 63)) - 1);
-            one_ |= (x & mk) != 0;
-            zero_ |= (~x & mk) != 0;
-        }
-        if (one_) atomicOr(&red[0], 1u);
-        if (zero_) atomicOr(&red[1], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < 2) J.flags[threadIdx.x] = red[threadIdx.x];
+    degen_body(J);
 }
 
 #endif
@@ -1071,7 +1099,7 @@ template <class F, int LGR>
 static hipError_t strided_one(const PassLaunch &p, const KArgs &ka0, hipStream_t s) {
     const KArgs &ka = ka0;
 #define L1(M, Q)                                                                                 \
-    hipLaunchKernelGGL((k_strided<F, LGR, M, Q>), dim3((unsigned)p.tiles, p.njobs), \
+    hipLaunchKernelGGL((k_strided<F, LGR, M, Q>), dim3((unsigned)p.tiles, p.njobs, p.which < 0 ? 2u : 1u), \
                        dim3(Tile<F, LGR, true, 1, M>::NT), 0, s, ka)
     // last inverse pass: rows j + t R/RL of group j come out of its last step's
     // output t, so the first out_rows rows need t < ceil(out_rows RL / R)
@@ -1331,30 +1359,32 @@ hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, c
     return hipGetLastError();
 }
 
-hipError_t launch_embed(uint32_t njobs, uint64_t max_L, const JobDev *jobs, const JobDev *one, hipStream_t s) {
+hipError_t launch_embed(uint32_t njobs, uint64_t max_L, const JobDev *jobs, const JobDev *one, bool degen,
+                        hipStream_t s) {
     JobDev o;
     if (one) o = *one;
     else std::memset(&o, 0, sizeof(o));
     uint64_t words = max_L >> 6;
     unsigned gx = (unsigned)umin64((words + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_embed, dim3(gx, njobs, 2), dim3(256), 0, s, jobs, o);
+    hipLaunchKernelGGL(k_embed, dim3(gx, njobs, degen ? 3 : 2), dim3(256), 0, s, jobs, o);
     return hipGetLastError();
 }
 
 hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint64_t rows, uint32_t njobs, const JobDev *jobs,
-                         const JobDev *one, hipStream_t s) {
+                         const JobDev *one, bool pack, hipStream_t s) {
     JobDev o;
     if (one) o = *one;
     else std::memset(&o, 0, sizeof(o));
     const int C = strided_cols(field == FIELD_GL ? 64 : 32, S_INV_PARITY);  // columns of the parity pass
     rows = (rows == 0 || rows > R) ? R : rows;
     dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((S / C + 63) / 64), njobs);
-    if (C == 8)
-        hipLaunchKernelGGL(k_ptrans<8>, grid, dim3(256), 0, s, jobs, o, R, S);
-    else if (C == 16)
-        hipLaunchKernelGGL(k_ptrans<16>, grid, dim3(256), 0, s, jobs, o, R, S);
-    else
-        hipLaunchKernelGGL(k_ptrans<32>, grid, dim3(256), 0, s, jobs, o, R, S);
+    if (C == 16) {
+        if (pack) hipLaunchKernelGGL((k_ptrans<16, true>), grid, dim3(256), 0, s, jobs, o, R, S);
+        else hipLaunchKernelGGL((k_ptrans<16, false>), grid, dim3(256), 0, s, jobs, o, R, S);
+    } else {
+        if (pack) hipLaunchKernelGGL((k_ptrans<32, true>), grid, dim3(256), 0, s, jobs, o, R, S);
+        else hipLaunchKernelGGL((k_ptrans<32, false>), grid, dim3(256), 0, s, jobs, o, R, S);
+    }
     return hipGetLastError();
 }
 
