@@ -109,7 +109,7 @@ def _profile_blob(path: str, sources):
 def _kernel_name(label: str) -> str:
     kind = label.split("[")[0]
     f = dict(kv.split("=") for kv in label.split("[")[1].rstrip("]").split(",")[1:])
-    field = "FGL" if "[u64" in label else "FP0" if "[p0" in label else "FBB"
+    field = "FGL" if "[u64" in label else "FP0" if "[p0" in label else "FLZ" if "[lz" in label else "FBB"
     return "k_%s<%s, %s, %s>" % (kind, field, f["lgr"], f["mode"])
 
 

@@ -24,7 +24,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-value", "-Wno-unused-result",
 ]
-NTT_PARTS = 8
+NTT_PARTS = 10
 # The Von Neumann kernel takes its next tile's ticket with one lane and reads it
 # a whole tile later; LLVM's atomic optimizer would broadcast the result right
 # away and so wait for the atomic's round trip on every tile.

@@ -155,9 +155,18 @@ std::vector<typename F::T> table_pow(typename F::T base, size_t count) {
 // w_(2^TWIN_LG): entry (t, jm) of the block (rad, ns, inverse) is w_(ns rad)^(+-t jm)
 // = w_(2^TWIN_LG)^(+-t jm 2^TWIN_LG / (ns rad)).
 template <class F>
-std::vector<typename F::T> stockham_tables() {
-    const auto in = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << (F::LGMAX - TWIN_LG)), size_t(1) << TWIN_LG);
-    std::vector<typename F::T> out(2 * STK_DIR_WORDS);
+std::vector<typename F::TW> stockham_tables() {
+    // plain powers of w_(2^TWIN_LG); entries are stored in the field's in-pass form
+    std::vector<typename F::T> in(size_t(1) << TWIN_LG);
+    {
+        const typename F::T base = F::powmod(F::WMAX, uint64_t(1) << (F::LGMAX - TWIN_LG));
+        typename F::T acc = 1;
+        for (auto &v : in) {
+            v = acc;
+            acc = F::mulmod(acc, base);
+        }
+    }
+    std::vector<typename F::TW> out(2 * STK_DIR_WORDS);
     const int mask = (1 << TWIN_LG) - 1;
     for (int inv = 0; inv < 2; ++inv)
         for (int rad = 2; rad <= 16; rad *= 2)
@@ -166,7 +175,8 @@ std::vector<typename F::T> stockham_tables() {
                 for (int t = 1; t < rad; ++t)
                     for (int jm = 0; jm < ns; ++jm) {
                         const int e = t * jm * scale;
-                        out[stk_offset(rad, ns, inv != 0) + (uint64_t)(t - 1) * ns + jm] = in[inv ? (-e) & mask : e];
+                        out[stk_offset(rad, ns, inv != 0) + (uint64_t)(t - 1) * ns + jm] =
+                            F::to_stk(in[inv ? (-e) & mask : e]);
                     }
             }
     return out;
@@ -222,17 +232,26 @@ bool split_levels(int field, int lg, Plan &p) {
 }
 
 // The field of a plan: 15*2^27+1 up to its 2^27, then 3*2^30+1 (32-bit words
-// as well) up to 2^30, then Goldilocks. Every coefficient is at most the input
-// length n <= L, below all three primes.
-// force: 0 = automatic, 1 = 15*2^27+1, 2 = Goldilocks, 3 = 3*2^30+1 (testing aid)
+// as well) up to 2^30, then Goldilocks; below them all, 7*2^26+1 (lazy values) up
+// to its 2^26. Every coefficient is at most the input length n <= L, below every
+// prime used for that length.
+// force: 0 = automatic, 1 = 15*2^27+1, 2 = Goldilocks, 3 = 3*2^30+1, 5 = 7*2^26+1
+// (testing aids; 4 is the two-piece schedule, see plan_shape)
 int make_plan(uint64_t Lmin, int force, Plan &p) {
     p = Plan();
     p.lg = std::max(MIN_LG, ceil_log2(Lmin));
     if (p.lg > 32) return EXT_ETOOLARGE;
-    p.field = p.lg <= FBB::LGMAX ? FIELD_BB : p.lg <= FP0::LGMAX ? FIELD_P0 : FIELD_GL;
+    p.field = p.lg <= FLZ::LGMAX   ? FIELD_LZ
+              : p.lg <= FBB::LGMAX ? FIELD_BB
+              : p.lg <= FP0::LGMAX ? FIELD_P0
+                                   : FIELD_GL;
     if (force == 1) {
         if (p.lg > FBB::LGMAX) return EXT_ETOOLARGE;
         p.field = FIELD_BB;
+        p.lg = std::max(p.lg, 2 * MIN_LEVEL_LG);  // (one workgroup per job is the lazy field's)
+    } else if (force == 5) {
+        if (p.lg > FLZ::LGMAX) return EXT_ETOOLARGE;
+        p.field = FIELD_LZ;
     } else if (force == 2) {
         p.field = FIELD_GL;
         p.lg = std::max(p.lg, 2 * MIN_LEVEL_LG);
@@ -241,7 +260,7 @@ int make_plan(uint64_t Lmin, int force, Plan &p) {
         p.field = FIELD_P0;
         p.lg = std::max(p.lg, 2 * MIN_LEVEL_LG);
     }
-    if (p.field == FIELD_BB && p.lg <= max_small_lg()) {
+    if (p.field == FIELD_LZ && p.lg <= max_small_lg()) {
         p.small = true;
         return EXT_OK;
     }
@@ -381,6 +400,7 @@ uint64_t mont_K(int lg) {
 }
 uint64_t pointwise_K(const Plan &p) {
     if (p.field == FIELD_BB) return mont_K<FBB>(p.lg);
+    if (p.field == FIELD_LZ) return mont_K<FLZ>(p.lg);
     if (p.field == FIELD_P0) return mont_K<FP0>(p.lg);
     return FGL::powmod(FGL::powmod(2, p.lg), FGL::P - 2);
 }
@@ -530,11 +550,11 @@ namespace {
 // 2^27 and 3*2^30+1 above; -1 if no field has that length.
 int tune_field(int word_bits, int lg) {
     if (word_bits == 64) return lg <= FGL::LGMAX ? FIELD_GL : -1;
-    return lg <= FBB::LGMAX ? FIELD_BB : lg <= FP0::LGMAX ? FIELD_P0 : -1;
+    return lg <= FLZ::LGMAX ? FIELD_LZ : lg <= FBB::LGMAX ? FIELD_BB : lg <= FP0::LGMAX ? FIELD_P0 : -1;
 }
 
 bool valid_plan(const Plan &p) {
-    if (p.small) return p.field == FIELD_BB && p.lg >= MIN_LG && p.lg <= max_small_lg() && p.nlev == 0;
+    if (p.small) return p.field == FIELD_LZ && p.lg >= MIN_LG && p.lg <= max_small_lg() && p.nlev == 0;
     if (p.nlev < 2 || p.nlev > 4) return false;
     int sum = 0;
     for (int i = 0; i < p.nlev; ++i) {
@@ -738,7 +758,9 @@ struct Tracer {
 
 // "<kind>[<field>,lgr=<log2 transform size>,mode=<pass mode>,arr=<0: input, 1: seed>]"
 // field: u32 = 15*2^27+1, p0 = 3*2^30+1 (32-bit words), u64 = Goldilocks
-const char *field_tag(int field) { return field == FIELD_BB ? "u32" : field == FIELD_P0 ? "p0" : "u64"; }
+const char *field_tag(int field) {
+    return field == FIELD_BB ? "u32" : field == FIELD_P0 ? "p0" : field == FIELD_LZ ? "lz" : "u64";
+}
 std::string pass_label(const char *what, int field, int lgr, int mode, int which = 0) {
     char b[112];
     snprintf(b, sizeof b, "%s[%s,lgr=%d,mode=%d,arr=%d]", what, field_tag(field), lgr, mode, which);
@@ -1155,6 +1177,7 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
     if (ff && !strcmp(ff, "gl")) c->force_field = 2;
     if (ff && !strcmp(ff, "bb")) c->force_field = 1;
     if (ff && !strcmp(ff, "p0")) c->force_field = 3;
+    if (ff && !strcmp(ff, "lz")) c->force_field = 5;
     if (ff && !strcmp(ff, "p0x2")) c->force_field = 4;  // two-piece schedule wherever it can run
     // testing aid: the 64-bit piece schedule with pieces of this many input bits
     if (const char *pb = getenv("EXT_PIECE_BITS")) c->piece_bits = strtoull(pb, nullptr, 10);
@@ -1191,6 +1214,14 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
         auto stk = stockham_tables<F>();
         ok = ok && upload(FIELD_P0, 0, lo.data(), lo.size() * 4) && upload(FIELD_P0, 1, hi.data(), hi.size() * 4) &&
              upload(FIELD_P0, 2, stk.data(), stk.size() * 4);
+    }
+    {
+        using F = FLZ;  // between passes Montgomery form; in-pass Shoup pairs (8 bytes)
+        auto lo = table_pow<F>(F::WMAX, size_t(1) << 16);
+        auto hi = table_pow<F>(F::powmod(F::WMAX, uint64_t(1) << 16), size_t(1) << (F::LGMAX - 16));
+        auto stk = stockham_tables<F>();
+        ok = ok && upload(FIELD_LZ, 0, lo.data(), lo.size() * 4) && upload(FIELD_LZ, 1, hi.data(), hi.size() * 4) &&
+             upload(FIELD_LZ, 2, stk.data(), stk.size() * 8);
     }
     if (ok) ok = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
@@ -1272,7 +1303,8 @@ int ext_tune_get(ext_ctx *c, int word_bits, int lg, int *nlev, int *lgr) {
         if (it != c->tuned.end()) p = it->second;
     }
     if (p.lg == 0) {
-        const int rc = make_plan(uint64_t(1) << lg, field == FIELD_GL ? 2 : field == FIELD_P0 ? 3 : 1, p);
+        const int rc = make_plan(uint64_t(1) << lg,
+                                 field == FIELD_GL ? 2 : field == FIELD_P0 ? 3 : field == FIELD_LZ ? 5 : 1, p);
         if (rc != EXT_OK) return rc;
     }
     if (nlev) *nlev = p.small ? 0 : p.nlev;
@@ -1619,7 +1651,7 @@ hipError_t enqueue_batch(ext_ctx *c, const BatchLayout &bl, JobDev *desc_dev, ui
         const unsigned wgs = std::min<unsigned>(bl.cls.total_items, (unsigned)(2 * cus));
         Tracer tr(c, s, capturing);
         tr.begin();
-        e = launch_small_batch(bl.cls, desc_dev, counter, wgs, c->tb[FIELD_BB], s);
+        e = launch_small_batch(bl.cls, desc_dev, counter, wgs, c->tb[FIELD_LZ], s);
         tr.end("small_persist");
         if (e != hipSuccess) return e;
     }

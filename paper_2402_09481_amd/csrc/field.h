@@ -19,6 +19,21 @@
 //        representative (< 2^64) of their class; only canon() returns the
 //        representative in [0, p). 2^64 = 2^32 - 1 (mod p) and 2^96 = -1 (mod p)
 //        give a multiply-free reduction of 128-bit products.
+//   FLZ: p = 7 * 2^26 + 1 (< 2^29), 32-bit words, L <= 2^26. Small enough that
+//        values can be kept lazily in [0, 4p) (4p < 2^31): a butterfly reduces
+//        its first operand to [0, 2p) with one compare-subtract, its second comes
+//        out of a product in [0, 2p) (or is reduced the same way), and the sum
+//        and the difference plus 2p need no reduction (Harvey's butterfly).
+//        Products by known constants (the in-register roots and the in-pass
+//        twiddles) are Shoup products: with w' = floor(w 2^32 / p), x w -
+//        mulhi(x, w') p lies in [0, 2p) for any x < 2^32. Products of two
+//        variables (the pointwise product) and the twiddles between passes
+//        (Montgomery-form tables) use Montgomery products, whose result lies
+//        in [0, 3p). Only canon() returns the representative in [0, p).
+//
+// Besides the values' type T every field names TW, the type of the in-pass
+// (Stockham) twiddle table entries: T itself, or for FLZ the pair w | w' << 32.
+// as_a / as_b prepare a butterfly's first / second operand for add and sub.
 //
 // Every field uses one fixed primitive root of unity w_max of order 2^LGMAX;
 // every transform of length L uses w_L = w_max^(2^LGMAX / L), so that all
@@ -32,6 +47,7 @@ namespace ext {
 // ------------------------------------------------------------ 15 * 2^27 + 1
 struct FBB {
     using T = uint32_t;
+    using TW = uint32_t;
     static constexpr uint32_t P = 0x78000001u;
     static constexpr uint32_t PINV = 2281701377u;  // P^-1 mod 2^32
     static constexpr int LGMAX = 27;
@@ -59,12 +75,14 @@ struct FBB {
         uint32_t r = hi - __umulhi(q, P);
         return umin(r, r + P);
     }
-    // multiply data by a twiddle stored in Montgomery form
+    // multiply data by a twiddle stored in Montgomery form (in-pass and between passes)
     __device__ static inline uint32_t mul_tw(uint32_t a, uint32_t tw) { return mont(a, tw); }
+    __device__ static inline uint32_t mul_ip(uint32_t a, uint32_t tw) { return mont(a, tw); }
     // product of two Montgomery-form twiddles, in Montgomery form
     __device__ static inline uint32_t tw_combine(uint32_t hi, uint32_t lo) { return mont(hi, lo); }
     __device__ static inline uint32_t canon(uint32_t a) { return a; }
     __device__ static inline uint32_t from_bit(uint32_t b) { return b; }
+    __device__ static inline uint32_t as_a(uint32_t v) { return v; }
     __device__ static inline uint32_t as_b(uint32_t v) { return v; }
     // x * w_RAD^K with the root's Montgomery form as a compile-time constant
     template <int RAD, int K>
@@ -86,11 +104,13 @@ struct FBB {
     __host__ __device__ static constexpr uint32_t to_tw(uint32_t w) {  // Montgomery form
         return (uint32_t)(((uint64_t)w << 32) % P);
     }
+    __host__ __device__ static constexpr uint32_t to_stk(uint32_t w) { return to_tw(w); }
 };
 
 // ------------------------------------------------------------ 3 * 2^30 + 1
 struct FP0 {
     using T = uint32_t;
+    using TW = uint32_t;
     static constexpr uint32_t P = 0xC0000001u;
     static constexpr uint32_t PINV = 1073741825u;  // P^-1 mod 2^32
     static constexpr int LGMAX = 30;
@@ -123,9 +143,11 @@ struct FP0 {
         return sub(hi, m);
     }
     __device__ static inline uint32_t mul_tw(uint32_t a, uint32_t tw) { return mont(a, tw); }
+    __device__ static inline uint32_t mul_ip(uint32_t a, uint32_t tw) { return mont(a, tw); }
     __device__ static inline uint32_t tw_combine(uint32_t hi, uint32_t lo) { return mont(hi, lo); }
     __device__ static inline uint32_t canon(uint32_t a) { return a; }
     __device__ static inline uint32_t from_bit(uint32_t b) { return b; }
+    __device__ static inline uint32_t as_a(uint32_t v) { return v; }
     __device__ static inline uint32_t as_b(uint32_t v) { return v; }
     template <int RAD, int K>
     __device__ static inline uint32_t mul_root(uint32_t x);
@@ -145,11 +167,13 @@ struct FP0 {
     __host__ __device__ static constexpr uint32_t to_tw(uint32_t w) {  // Montgomery form
         return (uint32_t)(((uint64_t)w << 32) % P);
     }
+    __host__ __device__ static constexpr uint32_t to_stk(uint32_t w) { return to_tw(w); }
 };
 
 // ------------------------------------------------------------ Goldilocks 2^64 - 2^32 + 1
 struct FGL {
     using T = uint64_t;
+    using TW = uint64_t;
     static constexpr uint64_t P = 0xFFFFFFFF00000001ull;
     static constexpr uint64_t EPS = 0xFFFFFFFFull;  // 2^64 mod P
     static constexpr int LGMAX = 32;
@@ -256,9 +280,12 @@ struct FGL {
     }
     __device__ static inline uint64_t mont(uint64_t a, uint64_t b) { return mul(a, b); }
     __device__ static inline uint64_t mul_tw(uint64_t a, uint64_t tw) { return mul(a, tw); }
+    __device__ static inline uint64_t mul_ip(uint64_t a, uint64_t tw) { return mul(a, tw); }
     __device__ static inline uint64_t tw_combine(uint64_t hi, uint64_t lo) { return mul(hi, lo); }
     __device__ static inline uint64_t from_bit(uint32_t b) { return b; }
-    // operand prepared for add/sub as their second argument
+    // operands prepared for add/sub: the first may be any representative, the
+    // second must be canonical
+    __device__ static inline uint64_t as_a(uint64_t v) { return v; }
     __device__ static inline uint64_t as_b(uint64_t v) { return canon(v); }
 
     __host__ __device__ static constexpr uint64_t mulmod(uint64_t a, uint64_t b) {
@@ -274,6 +301,77 @@ struct FGL {
         return r;
     }
     __host__ __device__ static constexpr uint64_t to_tw(uint64_t w) { return w; }
+    __host__ __device__ static constexpr uint64_t to_stk(uint64_t w) { return w; }
+};
+
+// ------------------------------------------------------------ 7 * 2^26 + 1, lazy
+struct FLZ {
+    using T = uint32_t;
+    using TW = uint64_t;  // Shoup pair: w | w' << 32, w' = floor(w 2^32 / P)
+    static constexpr uint32_t P = 469762049u;     // 7 * 2^26 + 1
+    static constexpr uint32_t P2 = 2 * P;
+    static constexpr uint32_t PINV = 3825205249u; // P^-1 mod 2^32
+    static constexpr int LGMAX = 26;
+    static constexpr uint32_t WMAX = 2187u;       // 3^7: order 2^26 (3 generates the group)
+    static constexpr uint32_t R_MOD_P = 67108855u; // 2^32 mod P (Montgomery form of 1)
+    static constexpr int WORD_BITS = 32;
+
+    __host__ __device__ static constexpr uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+    // [0, 4P) -> [0, 2P): if v >= 2P, v - 2P < v; otherwise v - 2P wraps above v
+    __device__ static inline uint32_t red2(uint32_t v) { return umin(v, v - P2); }
+    __device__ static inline uint32_t as_a(uint32_t v) { return red2(v); }
+    __device__ static inline uint32_t as_b(uint32_t v) { return red2(v); }
+    // a, b in [0, 2P): a + b and a - b + 2P lie in [0, 4P)
+    __device__ static inline uint32_t add(uint32_t a, uint32_t b) { return a + b; }
+    __device__ static inline uint32_t sub(uint32_t a, uint32_t b) { return a - b + P2; }
+    // Shoup product x w for x < 2^32, w < P, wq = floor(w 2^32 / P): with
+    // q = floor(x wq / 2^32), x w - q P lies in [0, 2P); computed mod 2^32
+    __device__ static inline uint32_t shoup(uint32_t x, uint32_t w, uint32_t wq) {
+        const uint32_t q = __umulhi(x, wq);
+        return x * w - q * P;
+    }
+    __device__ static inline uint32_t mul_tw(uint32_t a, uint64_t tw) {
+        return shoup(a, (uint32_t)tw, (uint32_t)(tw >> 32));
+    }
+    // Montgomery product a b 2^-32 for a, b < 4P: a b < 16 P^2, so its high half
+    // is below 16 P^2 / 2^32 < 2P; hi - mulhi(q, P) lies in (-P, 2P), and + P puts
+    // it in (0, 3P)
+    __device__ static inline uint32_t mont(uint32_t a, uint32_t b) {
+        const uint32_t lo = a * b;
+        const uint32_t hi = __umulhi(a, b);
+        const uint32_t q = lo * PINV;
+        return hi - __umulhi(q, P) + P;
+    }
+    // between passes: twiddles in Montgomery form
+    __device__ static inline uint32_t mul_ip(uint32_t a, uint32_t tw) { return mont(a, tw); }
+    __device__ static inline uint32_t tw_combine(uint32_t hi, uint32_t lo) { return mont(hi, lo); }
+    __device__ static inline uint32_t canon(uint32_t a) {
+        const uint32_t b = red2(a);
+        return umin(b, b - P);
+    }
+    __device__ static inline uint32_t from_bit(uint32_t b) { return b; }
+    template <int RAD, int K>
+    __device__ static inline uint32_t mul_root(uint32_t x);
+
+    __host__ __device__ static constexpr uint32_t mulmod(uint32_t a, uint32_t b) {
+        return (uint32_t)((uint64_t)a * b % P);
+    }
+    __host__ __device__ static constexpr uint32_t powmod(uint32_t a, uint64_t e) {
+        uint32_t r = 1;
+        while (e) {
+            if (e & 1) r = mulmod(r, a);
+            a = mulmod(a, a);
+            e >>= 1;
+        }
+        return r;
+    }
+    __host__ __device__ static constexpr uint32_t to_tw(uint32_t w) {  // Montgomery form
+        return (uint32_t)(((uint64_t)w << 32) % P);
+    }
+    __host__ __device__ static constexpr uint32_t shoup_q(uint32_t w) { return (uint32_t)(((uint64_t)w << 32) / P); }
+    __host__ __device__ static constexpr uint64_t to_stk(uint32_t w) {
+        return (uint64_t)w | ((uint64_t)shoup_q(w) << 32);
+    }
 };
 
 template <int RAD, int K>
@@ -288,18 +386,15 @@ __device__ inline uint32_t FP0::mul_root(uint32_t x) {
     return mont(x, FP0::to_tw(w));
 }
 
-// Compile-time table of the RAD-th roots of unity w_RAD^k (k < RAD) in twiddle form.
-template <class F, int RAD>
-struct RootsOf {
-    typename F::T w[RAD];
-    constexpr RootsOf() : w() {
-        typename F::T r = F::powmod(F::WMAX, (uint64_t(1) << F::LGMAX) / RAD);
-        typename F::T acc = 1;
-        for (int k = 0; k < RAD; ++k) {
-            w[k] = F::to_tw(acc);
-            acc = F::mulmod(acc, r);
-        }
-    }
-};
+static_assert((uint32_t)(FLZ::P * FLZ::PINV) == 1u, "PINV is the inverse of P mod 2^32");
+static_assert((uint64_t(1) << 32) % FLZ::P == FLZ::R_MOD_P, "R mod P");
+static_assert(uint64_t(4) * FLZ::P < (uint64_t(1) << 31), "lazy values below 4P fit 31 bits");
+static_assert(FLZ::powmod(FLZ::WMAX, uint64_t(1) << 25) == FLZ::P - 1, "w_max has order 2^26");
+
+template <int RAD, int K>
+__device__ inline uint32_t FLZ::mul_root(uint32_t x) {
+    constexpr uint32_t w = FLZ::powmod(FLZ::powmod(FLZ::WMAX, (uint64_t(1) << FLZ::LGMAX) / RAD), K);
+    return shoup(x, w, FLZ::shoup_q(w));
+}
 
 }  // namespace ext

@@ -87,8 +87,8 @@ __host__ __device__ constexpr uint64_t stk_offset(int rad, int ns, bool inv) {
 }
 
 // Field selector for the launchers.
-enum FieldId : int { FIELD_BB = 0, FIELD_GL = 1, FIELD_P0 = 2 };
-constexpr int NFIELDS = 3;
+enum FieldId : int { FIELD_BB = 0, FIELD_GL = 1, FIELD_P0 = 2, FIELD_LZ = 3 };
+constexpr int NFIELDS = 4;
 
 // Tile geometry (host copy of the kernels' compile-time choices).
 struct Geometry {
@@ -137,7 +137,7 @@ struct PassLaunch {
 
 hipError_t launch_strided(const PassLaunch &p, const Tables &t, hipStream_t s);
 hipError_t launch_contig(const PassLaunch &p, const Tables &t, hipStream_t s);
-// Whole extraction in one workgroup (field FBB, L = 2^lg <= 2^14).
+// Whole extraction in one workgroup (field FLZ, L = 2^lg <= 2^14).
 hipError_t launch_small(int lg, uint32_t njobs, const JobDev *jobs, const JobDev *one, const Tables &t,
                         hipStream_t s);
 // Size classes of a persistent small-job launch (jobs sorted by class).

@@ -45,7 +45,7 @@
 #include "field.h"
 #include "kernels.h"
 
-// The file is compiled once per part (NTT_PART = 0..7) so that the template
+// The file is compiled once per part (NTT_PART = 0..9) so that the template
 // instantiations build in parallel; without NTT_PART everything is built.
 #ifndef NTT_PART
 #define NTT_PART -1
@@ -114,7 +114,7 @@ __device__ inline void dft_layer_k(typename F::T *u) {
     if constexpr (K < LEN / 2) {
 #pragma unroll
         for (int s = 0; s < RAD; s += LEN) {
-            typename F::T a = u[s + K];
+            typename F::T a = F::as_a(u[s + K]);
             typename F::T b = u[s + K + LEN / 2];
             if constexpr (K == 0)
                 b = F::as_b(b);
@@ -265,7 +265,7 @@ struct Tile {
     // many as the LDS admits (160 KiB per CU, 4 SIMDs), at most 8. A register
     // count above that would leave LDS idle and halve the resident workgroups
     // (the bit-reading first pass of 32-bit fields needed 72 registers for 64).
-    static constexpr int LDS_BYTES = LDS_WORDS * (int)sizeof(T);
+    static constexpr int LDS_BYTES = TILE_WORDS * (int)sizeof(T) + STW_WORDS * (int)sizeof(typename F::TW);
     static constexpr int WG_BY_LDS = (160 * 1024) / LDS_BYTES;
     static constexpr int WPE0 = WG_BY_LDS * (NT / 64) / 4;
     static constexpr int WAVES_PER_SIMD = WPE0 < 1 ? 1 : (WPE0 > 8 ? 8 : WPE0);
@@ -286,10 +286,10 @@ struct Tile {
 // Stockham step compute on registers v (EPT values = EPT/RAD groups of RAD).
 // Twiddles from the global blocks, or (LT) from the tile's LDS copy stw.
 template <class F, class Tl, int RAD, int NS, bool INV, bool LT = false>
-__device__ inline void step_compute(typename F::T *v, const Tables &tb, const typename F::T *stw = nullptr) {
-    using T = typename F::T;
+__device__ inline void step_compute(typename F::T *v, const Tables &tb, const typename F::TW *stw = nullptr) {
+    using TW = typename F::TW;
     static_assert(NS * RAD <= (1 << TWIN_LG) && RAD <= 16, "step beyond the Stockham twiddle blocks");
-    const T *tw = (const T *)tb.stk + stk_offset(RAD, NS, INV);
+    const TW *tw = (const TW *)tb.stk + stk_offset(RAD, NS, INV);
     if constexpr (LT) {
         if constexpr (Tl::stw_has(RAD, NS, INV)) tw = stw + Tl::stw_block(RAD, NS, INV);
     }
@@ -385,7 +385,7 @@ __device__ inline void exchange_halves(typename F::T *v, typename F::T *lds) {
 // last-step layout if s1 == NSTEPS). LDS exchanges in between.
 template <class F, class Tl, bool INV, int S, bool LT = false>
 __device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, const Tables &tb,
-                                      const typename F::T *stw = nullptr) {
+                                      const typename F::TW *stw = nullptr) {
     if constexpr (S < Tl::NSTEPS) {
         constexpr int RAD = Tl::radix(S, INV);
         constexpr int NS = Tl::span(S, INV);
@@ -456,8 +456,9 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
     // t+12), read from a 16 x 4 table built here by the same arithmetic.
     constexpr bool LUT = BITS && RF == 16;
     using Unit = UnitOf<C>;
+    using TW = typename F::TW;
     __shared__ T lds[Tl::TILE_WORDS];
-    __shared__ T stw[Tl::STW_WORDS > 0 ? Tl::STW_WORDS : 1];
+    __shared__ TW stw[Tl::STW_WORDS > 0 ? Tl::STW_WORDS : 1];
     __shared__ T lut[LUT ? 64 : 1];
 
     const JobDev &J = a.jobs ? a.jobs[blockIdx.y] : a.one;
@@ -477,7 +478,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
     // that follows step 0
     for (int s = 1; s < Tl::NSTEPS; ++s) {
         const int rad = Tl::radix(s, INV), ns = Tl::span(s, INV);
-        const T *src = (const T *)a.tb.stk + stk_offset(rad, ns, INV);
+        const TW *src = (const TW *)a.tb.stk + stk_offset(rad, ns, INV);
         for (int i = threadIdx.x; i < (rad - 1) * ns; i += NT) stw[Tl::stw_off(s, INV) + i] = gload(src + i);
     }
 
@@ -537,7 +538,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
                 x = gload(data + gi);
             }
             if constexpr (INV) {
-                x = F::mul_tw(x, wt);
+                x = F::mul_ip(x, wt);
                 if (t + 1 < RF) wt = F::tw_combine(wt, st);
             }
             v[q * RF + t] = x;
@@ -593,7 +594,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
             const int r = j + t * (R / RL);
             T x = v[q * RL + t];
             if constexpr (FWD) {
-                gstore(data + gi, F::mul_tw(x, wt));
+                gstore(data + gi, F::mul_ip(x, wt));
                 if (t + 1 < RL) wt = F::tw_combine(wt, st);
             } else if constexpr (MODE == S_INV) {
                 gstore(data + gi, x);
@@ -619,8 +620,9 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
     using T = typename F::T;
     constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
     constexpr bool FUSED = (MODE == C_FUSED || MODE == C_FUSED2);
+    using TW = typename F::TW;
     __shared__ T lds[C * Tl::RP];
-    __shared__ T stw[Tl::STW_WORDS > 0 ? Tl::STW_WORDS : 1];
+    __shared__ TW stw[Tl::STW_WORDS > 0 ? Tl::STW_WORDS : 1];
     // the small Stockham twiddle blocks of the forward transform, first read in
     // step 1, after the barrier that follows step 0
     if constexpr (Tl::LT) {
@@ -629,7 +631,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
         for (int s = 1; s < Tl::NSTEPS; ++s) {
             if (!Tl::stw_local(s, false)) continue;
             const int rad = Tl::radix(s, false), ns = Tl::span(s, false);
-            const T *src = (const T *)a.tb.stk + stk_offset(rad, ns, false);
+            const TW *src = (const TW *)a.tb.stk + stk_offset(rad, ns, false);
             for (int i = threadIdx.x; i < (rad - 1) * ns; i += Tl::NT) stw[Tl::stw_off(s, false) + i] = gload(src + i);
         }
     }
@@ -752,10 +754,11 @@ struct SmallTile {
 // the pointwise product, the inverse, parity, fold, pack, and the Dodis
 // degenerate-input check. Every thread of the workgroup must call this (it
 // contains workgroup barriers); `write` = false runs the arithmetic without
-// writing any output (idle groups of a persistent workgroup).
+// writing any output (idle groups of a persistent workgroup). Field FLZ
+// (7 * 2^26 + 1, lazy values).
 template <int LG>
 __device__ inline void small_body(const JobDev &J, bool write, uint32_t *lds, uint32_t *red, const Tables &tb) {
-    using F = FBB;
+    using F = FLZ;
     using Tl = SmallTile<LG>;
     using T = uint32_t;
     constexpr int R = Tl::R, EPT = Tl::EPT, NT = Tl::NT;
@@ -792,7 +795,7 @@ __device__ inline void small_body(const JobDev &J, bool write, uint32_t *lds, ui
         int c, j;
         Tl::template coords<RADI>(q, c, j);
 #pragma unroll
-        for (int t = 0; t < RADI; ++t) lds[Tl::lidx(0, j + t * (R / RADI))] = vb[q * RADI + t];
+        for (int t = 0; t < RADI; ++t) lds[Tl::lidx(0, j + t * (R / RADI))] = F::canon(vb[q * RADI + t]);
     }
     if (lt < 2) red[lt] = 0;
     __syncthreads();
@@ -1158,6 +1161,8 @@ hipError_t launch_strided_p0(const PassLaunch &p, const Tables &t, hipStream_t s
 hipError_t launch_contig_bb(const PassLaunch &p, const Tables &t, hipStream_t s);
 hipError_t launch_contig_gl(const PassLaunch &p, const Tables &t, hipStream_t s);
 hipError_t launch_contig_gl_hi(const PassLaunch &p, const Tables &t, hipStream_t s);  // rows of 2^11..2^13
+hipError_t launch_strided_lz(const PassLaunch &p, const Tables &t, hipStream_t s);
+hipError_t launch_contig_lz(const PassLaunch &p, const Tables &t, hipStream_t s);
 hipError_t launch_contig_p0(const PassLaunch &p, const Tables &t, hipStream_t s);
 
 #if NTT_HAS(0)
@@ -1229,6 +1234,36 @@ hipError_t launch_contig_gl_hi(const PassLaunch &p, const Tables &t, hipStream_t
 }
 #endif
 
+#if NTT_HAS(8)
+hipError_t launch_strided_lz(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    KArgs ka = make_args(p, t);
+    switch (p.lgr) {
+        case 7: return strided_one<FLZ, 7>(p, ka, s);
+        case 8: return strided_one<FLZ, 8>(p, ka, s);
+        case 9: return strided_one<FLZ, 9>(p, ka, s);
+        case 10: return strided_one<FLZ, 10>(p, ka, s);
+    }
+    return hipErrorInvalidValue;
+}
+#endif
+
+#if NTT_HAS(9)
+hipError_t launch_contig_lz(const PassLaunch &p, const Tables &t, hipStream_t s) {
+    KArgs ka = make_args(p, t);
+    switch (p.lgr) {
+        case 7: return contig_one<FLZ, 7>(p, ka, s);
+        case 8: return contig_one<FLZ, 8>(p, ka, s);
+        case 9: return contig_one<FLZ, 9>(p, ka, s);
+        case 10: return contig_one<FLZ, 10>(p, ka, s);
+        case 11: return contig_one<FLZ, 11>(p, ka, s);
+        case 12: return contig_one<FLZ, 12>(p, ka, s);
+        case 13: return contig_one<FLZ, 13>(p, ka, s);
+        case 14: return contig_one<FLZ, 14>(p, ka, s);
+    }
+    return hipErrorInvalidValue;
+}
+#endif
+
 #if NTT_HAS(5)
 hipError_t launch_strided_p0(const PassLaunch &p, const Tables &t, hipStream_t s) {
     KArgs ka = make_args(p, t);
@@ -1294,10 +1329,16 @@ static Geometry geo_c(int lgr) {
     return Geometry{0, 0};
 }
 Geometry strided_geometry(int field, int lgr, int mode) {
-    return field == FIELD_GL ? geo_s<FGL>(lgr, mode) : field == FIELD_P0 ? geo_s<FP0>(lgr, mode) : geo_s<FBB>(lgr, mode);
+    return field == FIELD_GL   ? geo_s<FGL>(lgr, mode)
+           : field == FIELD_P0 ? geo_s<FP0>(lgr, mode)
+           : field == FIELD_LZ ? geo_s<FLZ>(lgr, mode)
+                               : geo_s<FBB>(lgr, mode);
 }
 Geometry contig_geometry(int field, int lgr) {
-    return field == FIELD_GL ? geo_c<FGL>(lgr) : field == FIELD_P0 ? geo_c<FP0>(lgr) : geo_c<FBB>(lgr);
+    return field == FIELD_GL   ? geo_c<FGL>(lgr)
+           : field == FIELD_P0 ? geo_c<FP0>(lgr)
+           : field == FIELD_LZ ? geo_c<FLZ>(lgr)
+                               : geo_c<FBB>(lgr);
 }
 
 hipError_t launch_strided(const PassLaunch &p, const Tables &t, hipStream_t s) {
@@ -1305,6 +1346,7 @@ hipError_t launch_strided(const PassLaunch &p, const Tables &t, hipStream_t s) {
         case FIELD_BB: return launch_strided_bb(p, t, s);
         case FIELD_GL: return launch_strided_gl(p, t, s);
         case FIELD_P0: return launch_strided_p0(p, t, s);
+        case FIELD_LZ: return launch_strided_lz(p, t, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1313,6 +1355,7 @@ hipError_t launch_contig(const PassLaunch &p, const Tables &t, hipStream_t s) {
         case FIELD_BB: return launch_contig_bb(p, t, s);
         case FIELD_GL: return launch_contig_gl(p, t, s);
         case FIELD_P0: return launch_contig_p0(p, t, s);
+        case FIELD_LZ: return launch_contig_lz(p, t, s);
     }
     return hipErrorInvalidValue;
 }

@@ -2,7 +2,10 @@
 exact integer arithmetic: Goldilocks product, sum, difference, canonical form,
 every power-of-two multiplier 2^s (s < 192, the roots of the in-register DFTs
 among them) and the 128-bit reduction on arbitrary limbs; Montgomery product,
-sum and difference of the two 32-bit fields. Random operands plus the edge
+sum and difference of the two 32-bit fields; the lazy field 7*2^26+1 (values
+anywhere in [0, 4P)): Montgomery product, the butterfly's sum and difference with
+their operand preparation, canonical form, Shoup products by in-pass twiddle
+pairs and by the in-register roots, each with its output range. Random operands plus the edge
 values of each field (0, 1, P - 1, P and the non-canonical 64-bit values above P,
 products whose upper limbs are zero). The GPU parity tests check the same
 routines inside the kernels; these pin each routine on its own."""
@@ -33,6 +36,7 @@ def lib(tmp_path_factory):
     u32p = np.ctypeslib.ndpointer(np.uint32, flags="C")
     L.fgl_op.argtypes = [ctypes.c_int, u64p, u64p, u64p, ctypes.c_size_t]
     L.f32_op.argtypes = [ctypes.c_int, ctypes.c_int, u32p, u32p, u32p, ctypes.c_size_t]
+    L.flz_op.argtypes = [ctypes.c_int, u32p, u32p, u32p, ctypes.c_size_t]
     return L
 
 
@@ -110,3 +114,53 @@ def test_32bit_montgomery_add_sub(lib, field):
         got = [int(v) for v in out]
         bad = [(x, y, r) for x, y, r in zip(a, b, got) if r != ref(x, y)]  # canonical results
         assert not bad, (field, op, bad[:3])
+
+
+PLZ = 7 * (1 << 26) + 1
+
+
+def lz(L, op, a, b):
+    A = np.ascontiguousarray(a, np.uint32)
+    B = np.ascontiguousarray(b, np.uint32)
+    out = np.empty_like(A)
+    L.flz_op(op, A, B, out, len(A))
+    return [int(v) for v in out]
+
+
+def lazy_operands(n, seed, hi=4 * PLZ):
+    g = np.random.default_rng(seed)
+    edge = [0, 1, 2, PLZ - 1, PLZ, PLZ + 1, 2 * PLZ - 1, 2 * PLZ, 2 * PLZ + 1, 3 * PLZ, 4 * PLZ - 2, hi - 1]
+    a = [x for x in edge for _ in edge] + [int(v) for v in g.integers(0, hi, size=n)]
+    b = [y for _ in edge for y in edge] + [int(v) for v in g.integers(0, hi, size=n)]
+    return a, b
+
+
+def test_lazy_field_mont_add_sub_canon(lib):
+    a, b = lazy_operands(60000, 20)
+    rinv = pow(1 << 32, -1, PLZ)
+    got = lz(lib, 0, a, b)
+    assert all(r % PLZ == x * y * rinv % PLZ and r < 3 * PLZ for x, y, r in zip(a, b, got))
+    got = lz(lib, 1, a, b)
+    assert all(r % PLZ == (x + y) % PLZ and r < 4 * PLZ for x, y, r in zip(a, b, got))
+    got = lz(lib, 2, a, b)
+    assert all(r % PLZ == (x - y) % PLZ and r < 4 * PLZ for x, y, r in zip(a, b, got))
+    got = lz(lib, 3, a, b)
+    assert all(r == x % PLZ for x, r in zip(a, got))
+
+
+def test_lazy_field_shoup_products(lib):
+    g = np.random.default_rng(21)
+    # any 32-bit x (the Shoup bound holds for x < 2^32), twiddles w < P
+    x = [0, 1, 4 * PLZ - 1, (1 << 32) - 1] * 4 + [int(v) for v in g.integers(0, 1 << 32, size=60000, dtype=np.uint64)]
+    w = [0, 1, PLZ - 1, PLZ // 2] * 4 + [int(v) for v in g.integers(0, PLZ, size=60000)]
+    got = lz(lib, 4, x, w)
+    assert all(r % PLZ == xi * wi % PLZ and r < 2 * PLZ for xi, wi, r in zip(x, w, got))
+    # the in-register roots: w_RAD^k = WMAX^(2^26 k / RAD), WMAX = 3^7 of order 2^26
+    wmax = pow(3, 7, PLZ)
+    assert pow(wmax, 1 << 25, PLZ) == PLZ - 1
+    xs = x[:5000]
+    for op, rad in ((5, 2), (6, 4), (7, 8), (8, 16)):
+        for k in range(rad):
+            w = pow(wmax, (1 << 26) // rad * k, PLZ)
+            got = lz(lib, op, xs, [k] * len(xs))
+            assert all(r % PLZ == xi * w % PLZ and r < 2 * PLZ for xi, r in zip(xs, got)), (rad, k)

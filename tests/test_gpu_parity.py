@@ -1,4 +1,7 @@
-"""GPU parity: the HIP path against the oracle, bit for bit, through the C-ABI."""
+"""GPU parity: the HIP path against the oracle, bit for bit, through the C-ABI.
+Default contexts run transforms up to 2^26 over the lazy field 7*2^26+1 (one
+workgroup per job up to 2^14); the forced-field contexts cover 15*2^27+1,
+3*2^30+1 and the 64-bit field at small sizes."""
 import os
 
 import numpy as np
@@ -38,6 +41,21 @@ def ctx_p0():
     from 2^28 to 2^30), multi-pass, at small sizes."""
     import paper_2402_09481_amd as P
     os.environ["EXT_FORCE_FIELD"] = "p0"
+    try:
+        c = P.Context(0)
+    finally:
+        del os.environ["EXT_FORCE_FIELD"]
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_bb():
+    """A context that runs every shape on 15*2^27+1 (the 32-bit field of transforms of
+    2^27; below that the lazy field 7*2^26+1 runs by default), multi-pass, at small
+    sizes."""
+    import paper_2402_09481_amd as P
+    os.environ["EXT_FORCE_FIELD"] = "bb"
     try:
         c = P.Context(0)
     finally:
@@ -176,6 +194,15 @@ def test_p0_field_path(ctx_p0, kind, n, m):
     run_case(ctx_p0, kind, n, m, "paper", seed=5 * n + m)
     if kind == "toeplitz":
         run_case(ctx_p0, kind, n, m, "linear", seed=7 * n + m)
+
+
+@pytest.mark.parametrize("kind,n,m", [("toeplitz", 9000, 7000), ("toeplitz", 100000, 50000), ("toeplitz", 129, 64),
+                                      ("toeplitz", 1 << 20, 1 << 19), ("toeplitz", (1 << 22) + 5, 1 << 21),
+                                      ("dodis", 8219, 8219), ("circulant", 16420, 8000)])
+def test_bb_field_path(ctx_bb, kind, n, m):
+    run_case(ctx_bb, kind, n, m, "paper", seed=17 * n + m)
+    if kind == "toeplitz":
+        run_case(ctx_bb, kind, n, m, "linear", seed=19 * n + m)
 
 
 @pytest.mark.parametrize("n,m", [(128, 1), (129, 64), (200, 199), (1000, 1), (4097, 2048), (9000, 7000),
