@@ -791,7 +791,8 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
     const uint64_t L = uint64_t(1) << p.lg;
     hipError_t e;
     tr.begin();
-    e = launch_embed(njobs, L, jobs_dev, one, any_degen, s);
+    e = launch_embed(njobs, L, p.lgr[0], strided_geometry(p.field, p.lgr[0], S_FWD_BITS).C, jobs_dev, one, any_degen,
+                     s);
     if (tr.on) tr.end("embed");
     if (e != hipSuccess) return e;
     // the operands transformed here: both (-1), or only the seed (SEED_ONLY) or only

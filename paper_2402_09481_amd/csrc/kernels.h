@@ -154,10 +154,11 @@ hipError_t launch_small_batch(const SmallClasses &cls, const JobDev *jobs, uint3
                               const Tables &t, hipStream_t s);
 // Packed parity -> z (fold, mask, degenerate check result, status).
 hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, const JobDev *one, hipStream_t s);
-// Lay out both inputs as L-bit coefficient strings (eb[0], eb[1]); with degen, also
-// the Dodis degenerate-input check (flags).
-hipError_t launch_embed(uint32_t njobs, uint64_t max_L, const JobDev *jobs, const JobDev *one, bool degen,
-                        hipStream_t s);
+// Lay out both inputs as L-bit coefficient strings (eb[0], eb[1]) in the unit
+// layout of the first strided level (2^lgr0 rows, C-bit units, tile-major); with
+// degen, also the Dodis degenerate-input check (flags). Every job has length L.
+hipError_t launch_embed(uint32_t njobs, uint64_t L, int lgr0, int C, const JobDev *jobs, const JobDev *one,
+                        bool degen, hipStream_t s);
 // Tile-major parity units of the last inverse pass -> packed natural order, rows
 // [0, rows) of R (the rows that hold needed coefficients): into pb, or with pack
 // straight into z (tail bits cleared, degenerate check applied, status written;

@@ -528,10 +528,12 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
             T x;
             if constexpr (BITS) {
                 // a row segment of the tile is C adjacent bits starting at a
-                // multiple of C: one C-bit unit, the same address for every
-                // lane of the row
-                const Unit *ub = (const Unit *)J.eb[which];
-                const uint32_t bit = (uint32_t)(gload(ub + (gi - c) / C) >> c) & 1u;
+                // multiple of C: one C-bit unit, the same address for every lane
+                // of the row. The embedding lays the units out tile-major (unit of
+                // row r of column tile ct at ct R + r), so a tile's rows are
+                // consecutive units and a wave's loads fall in one cache line.
+                const Unit *ub = (const Unit *)J.eb[which] + ct * R;
+                const uint32_t bit = (uint32_t)(gload(ub + j + t * (R / RF)) >> c) & 1u;
                 if constexpr (LUT) bt[q * RF + t] = bit;
                 x = F::from_bit(bit);
             } else {
@@ -935,21 +937,42 @@ __device__ inline void degen_body(const JobDev &J) {
     if (threadIdx.x < 2) J.flags[threadIdx.x] = red[threadIdx.x];
 }
 
+// The embedded L-bit coefficient strings, in the unit layout the first strided
+// level reads: the transform viewed as R = 2^lgr0 rows of S = L / R coefficients,
+// the C-bit unit of row r and column tile ct (coefficients r S + ct C ..) at unit
+// index ct R + r. A workgroup takes 64 rows by up to 16 words of each row: it
+// assembles the words (coalesced along the rows' words) in LDS, then writes each
+// column tile's 64 row units as one contiguous run.
 // blockIdx.z = 0, 1: the embedding of x, y; z = 2 (launched for shapes with the
 // degenerate check): the check, by the first workgroup of the slice.
-__global__ void __launch_bounds__(256) k_embed(const JobDev *jobs, JobDev one) {
+template <int C>
+__global__ void __launch_bounds__(256) k_embed(const JobDev *jobs, JobDev one, uint32_t lgr0, uint32_t row_groups) {
+    using Unit = UnitOf<C>;
+    constexpr int UPW = 64 / C;  // units per word
     const JobDev &J = jobs ? jobs[blockIdx.y] : one;
     if (blockIdx.z == 2) {
         if (blockIdx.x == 0) degen_body(J);
         return;
     }
+    __shared__ uint64_t tl[64][17];
     // (the descriptor is read once: the stores could alias it)
-    const uint64_t L = J.L, nw = L >> 6;
+    const uint64_t L = J.L, R = uint64_t(1) << lgr0, wpr = (L >> lgr0) >> 6;  // words per row
     const int which = blockIdx.z;
     const Emb e = which ? J.ey : J.ex;
-    uint64_t *const dst = J.eb[which];
-    for (uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x; w < nw; w += (uint64_t)gridDim.x * 256)
-        gstore(dst + w, embed_word(e, L, w));
+    Unit *const dst = (Unit *)J.eb[which];
+    const uint64_t rg = blockIdx.x % row_groups, kg = blockIdx.x / row_groups;
+    const uint64_t r0 = rg * 64, k0 = kg * 16;
+    const int nk = (int)umin64(16, wpr - k0);
+    for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+        const int rr = i >> 4, kk = i & 15;
+        if (kk < nk) tl[rr][kk] = embed_word(e, L, (r0 + rr) * wpr + k0 + kk);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * nk * UPW; i += 256) {
+        const int rr = i & 63, uu = i >> 6;  // 64 consecutive rows of one column tile
+        const Unit u = (Unit)(tl[rr][uu / UPW] >> ((uu % UPW) * C));
+        gstore(dst + (k0 * UPW + uu) * R + r0 + rr, u);
+    }
 }
 
 // ------------------------------------------------------------------ persistent batch of small jobs
@@ -1402,14 +1425,21 @@ hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, c
     return hipGetLastError();
 }
 
-hipError_t launch_embed(uint32_t njobs, uint64_t max_L, const JobDev *jobs, const JobDev *one, bool degen,
-                        hipStream_t s) {
+hipError_t launch_embed(uint32_t njobs, uint64_t L, int lgr0, int C, const JobDev *jobs, const JobDev *one,
+                        bool degen, hipStream_t s) {
     JobDev o;
     if (one) o = *one;
     else std::memset(&o, 0, sizeof(o));
-    uint64_t words = max_L >> 6;
-    unsigned gx = (unsigned)umin64((words + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_embed, dim3(gx, njobs, degen ? 3 : 2), dim3(256), 0, s, jobs, o);
+    const uint64_t R = uint64_t(1) << lgr0, wpr = (L >> lgr0) >> 6;
+    if (R % 64 || wpr == 0) return hipErrorInvalidValue;
+    const uint64_t row_groups = R / 64, word_groups = (wpr + 15) / 16;
+    const dim3 grid((unsigned)(row_groups * word_groups), njobs, degen ? 3 : 2);
+    if (C == 16)
+        hipLaunchKernelGGL((k_embed<16>), grid, dim3(256), 0, s, jobs, o, (uint32_t)lgr0, (uint32_t)row_groups);
+    else if (C == 32)
+        hipLaunchKernelGGL((k_embed<32>), grid, dim3(256), 0, s, jobs, o, (uint32_t)lgr0, (uint32_t)row_groups);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
