@@ -133,10 +133,16 @@ def valu_view(label: str, avg_ms: float):
         return None
     lane_ops = e["valu_insts"] * 64
     achieved = lane_ops / (avg_ms * 1e-3) / 1e12
-    return {"lane_ops_per_launch": int(lane_ops), "achieved": round(achieved, 2), "peak": round(VALU_PEAK_T, 2),
-            "unit": "T lane-op/s", "frac": round(achieved / VALU_PEAK_T, 4),
-            "note": "peak = one wave64 instruction per 4 cycles per SIMD (32-bit multiplies, carries, "
-                    "64-bit adds); plain 32-bit adds, logic and moves issue faster, so frac can pass 1"}
+    out = {"lane_ops_per_launch": int(lane_ops), "achieved": round(achieved, 2), "peak": round(VALU_PEAK_T, 2),
+           "unit": "T lane-op/s", "frac": round(achieved / VALU_PEAK_T, 4),
+           "note": "peak = one wave64 instruction per 4 cycles per SIMD at 2.4 GHz (32-bit multiplies, carries, "
+                   "64-bit adds); plain 32-bit adds, logic and moves issue faster, so frac can pass 1"}
+    if e.get("gpu_cycles"):
+        # the profile's own cycle count (GRBM_GUI_ACTIVE / 8 XCDs): the clock the kernel ran at
+        # and its VALU issue rate against one wave64 instruction per 4 cycles per SIMD
+        out["profiled_clock_ghz"] = round(e["gpu_cycles"] / (e["duration_ms"] * 1e-3) / 1e9, 3)
+        out["profiled_issue_rate"] = round(e["valu_insts"] * 4 / (1024 * e["gpu_cycles"]), 3)
+    return out
 
 
 def profiled_vn_traffic(n: int):
