@@ -64,10 +64,11 @@ extern "C" {
 #define EXT_SEED_LINEAR 1u
 /* Wait for the stream and return the device status. */
 #define EXT_SYNC 2u
-/* extract_batch only: capture the batch's launch sequence into a HIP graph on
+/* extract_batch only: record the batch's launch sequence as a HIP graph on
  * first use of a batch signature (the multiset of transform sizes) and replay it
  * afterwards. Worth it when the same signature repeats; without the flag the
- * grouped launches are enqueued directly. */
+ * grouped launches are enqueued directly. The graph is built node by node, not
+ * by stream capture, so other host threads may use the device meanwhile. */
 #define EXT_GRAPH 4u
 /* Single calls: keep the seed's transform in HBM and reuse it. A strong seeded
  * extractor may use one seed for many input blocks (the theorem on extractors
@@ -198,7 +199,7 @@ typedef struct ext_job {
  * sizes (transform length <= 2^14) run in one persistent launch that takes
  * jobs from a work counter, larger sizes as batched multi-pass launches, one
  * set per size class. With EXT_GRAPH the launch sequence of a batch signature
- * is captured once into a HIP graph and replayed. `jobs` is a host array of
+ * is recorded once as a HIP graph and replayed. `jobs` is a host array of
  * `count` entries. Each job is validated on the host first and gets job.err;
  * invalid jobs are skipped (their z untouched). Returns EXT_OK if every job
  * was enqueued, the first failing job's code if some were skipped, or a

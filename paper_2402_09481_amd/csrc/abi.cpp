@@ -498,7 +498,6 @@ struct ext_ctx {
     uint64_t piece_bits = 0;  // testing aid: piece schedule for every sum longer than this
     void *scratch = nullptr;  // this device's allocation-free workspace (noalloc_scratch_address)
     std::map<int, Plan> tuned;  // key: field * 64 + lg
-    hipStream_t capture_stream = nullptr;
     // pinned status words for EXT_SYNC calls without a status pointer
     std::vector<int32_t *> pinned_status;
     // batch graph cache
@@ -520,8 +519,8 @@ struct ext_ctx {
     };
     std::map<std::string, GraphEntry> graphs;
     // held by a graph-mode batch call from its cache lookup until its replay is
-    // enqueued: entries, their staging and the capture stream are used by one
-    // call at a time, and eviction never meets an entry in use
+    // enqueued: entries and their staging are used by one call at a time, and
+    // eviction never meets an entry in use
     std::mutex graph_mu;
     // transformed-seed cache
     struct SeedEntry {
@@ -1224,7 +1223,6 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
         ok = ok && upload(FIELD_LZ, 0, lo.data(), lo.size() * 4) && upload(FIELD_LZ, 1, hi.data(), hi.size() * 4) &&
              upload(FIELD_LZ, 2, stk.data(), stk.size() * 8);
     }
-    if (ok) ok = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         ext_destroy(c);
         return EXT_EDEVICE;
@@ -1266,7 +1264,6 @@ void ext_destroy(ext_ctx *c) {
         hipEventDestroy(mk.a);
         hipEventDestroy(mk.b);
     }
-    if (c->capture_stream) hipStreamDestroy(c->capture_stream);
     delete c;
 }
 
@@ -1805,11 +1802,18 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
         if (e == hipSuccess) e = hipEventRecord(ge->done[k], stream);
         ge->used[k] = true;
         if (e == hipSuccess && !ge->exec) {
+            // the launch sequence is recorded as the kernel nodes of a new graph
+            // (no stream capture: other host threads stay unaffected)
             hipGraph_t graph = nullptr;
-            e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) e = enqueue_batch(c, bl, ge->desc_dev, counter, c->capture_stream, true);
-            hipError_t e2 = hipStreamEndCapture(c->capture_stream, &graph);
-            if (e == hipSuccess) e = e2;
+            e = hipGraphCreate(&graph, 0);
+            if (e == hipSuccess) {
+                GraphRecorder rec;
+                rec.graph = graph;
+                set_graph_recorder(&rec);
+                e = enqueue_batch(c, bl, ge->desc_dev, counter, stream, true);
+                set_graph_recorder(nullptr);
+                if (e == hipSuccess) e = rec.err;
+            }
             if (e == hipSuccess) e = hipGraphInstantiate(&ge->exec, graph, nullptr, nullptr, 0);
             if (graph) hipGraphDestroy(graph);
             if (e != hipSuccess) ge->exec = nullptr;

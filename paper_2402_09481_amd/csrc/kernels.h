@@ -135,6 +135,19 @@ struct PassLaunch {
     const JobDev *one;    // host copy for single-job launches (passed by value)
 };
 
+// Graph recording without stream capture. While a thread has set a recorder,
+// every launcher below adds its kernel to rec->graph as a node that depends on
+// the previous one (rec->last), in launch order, instead of launching it on the
+// stream; the first failure is kept in rec->err. Stream capture is not used for
+// batch graphs because, on this runtime, a capture in progress makes
+// device-wide calls of other host threads fail (and is invalidated by them).
+struct GraphRecorder {
+    hipGraph_t graph = nullptr;
+    hipGraphNode_t last = nullptr;
+    hipError_t err = hipSuccess;
+};
+void set_graph_recorder(GraphRecorder *rec);  // this thread; nullptr ends recording
+
 hipError_t launch_strided(const PassLaunch &p, const Tables &t, hipStream_t s);
 hipError_t launch_contig(const PassLaunch &p, const Tables &t, hipStream_t s);
 // Whole extraction in one workgroup (field FLZ, L = 2^lg <= 2^14).

@@ -40,7 +40,9 @@
 //   small      whole extraction of one job in one workgroup (L <= 2^14)
 #include <algorithm>
 #include <cstring>
+#include <tuple>
 #include <type_traits>
+#include <utility>
 
 #include "field.h"
 #include "kernels.h"
@@ -53,6 +55,39 @@
 #define NTT_HAS(k) (NTT_PART < 0 || NTT_PART == (k))
 
 namespace ext {
+
+// ------------------------------------------------------------------ launching
+
+extern thread_local GraphRecorder *t_graph_recorder;
+
+// Launches kern on stream s, or adds it to the recording graph of this thread.
+// The arguments are converted to the kernel's parameter types first; both paths
+// pass pointers to those values (a graph node copies them when it is added).
+template <typename... P, typename... A>
+static hipError_t launch_k(void (*kern)(P...), dim3 grid, dim3 block, size_t shmem, hipStream_t s, A &&...args) {
+    static_assert(sizeof...(P) == sizeof...(A), "argument count");
+    std::tuple<std::decay_t<P>...> vals(std::forward<A>(args)...);
+    void *ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1];
+    std::apply([&](auto &...v) {
+        int i = 0;
+        ((ptrs[i++] = (void *)&v), ...);
+    }, vals);
+    if (GraphRecorder *r = t_graph_recorder) {
+        if (r->err != hipSuccess) return r->err;
+        hipKernelNodeParams kp = {};
+        kp.func = (void *)kern;
+        kp.gridDim = grid;
+        kp.blockDim = block;
+        kp.sharedMemBytes = (unsigned)shmem;
+        kp.kernelParams = ptrs;
+        kp.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        r->err = hipGraphAddKernelNode(&node, r->graph, r->last ? &r->last : nullptr, r->last ? 1 : 0, &kp);
+        if (r->err == hipSuccess) r->last = node;
+        return r->err;
+    }
+    return hipLaunchKernel((const void *)kern, grid, block, ptrs, shmem, s);
+}
 
 // ------------------------------------------------------------------ helpers
 
@@ -1124,14 +1159,15 @@ static KArgs make_args(const PassLaunch &p, const Tables &t) {
 template <class F, int LGR>
 static hipError_t strided_one(const PassLaunch &p, const KArgs &ka0, hipStream_t s) {
     const KArgs &ka = ka0;
-#define L1(M, Q)                                                                                 \
-    hipLaunchKernelGGL((k_strided<F, LGR, M, Q>), dim3((unsigned)p.tiles, p.njobs, p.which < 0 ? 2u : 1u), \
-                       dim3(Tile<F, LGR, true, 1, M>::NT), 0, s, ka)
+#define L1(M, Q)                                                                                        \
+    e = launch_k(k_strided<F, LGR, M, Q>, dim3((unsigned)p.tiles, p.njobs, p.which < 0 ? 2u : 1u), \
+                 dim3(Tile<F, LGR, true, 1, M>::NT), 0, s, ka)
     // last inverse pass: rows j + t R/RL of group j come out of its last step's
     // output t, so the first out_rows rows need t < ceil(out_rows RL / R)
     constexpr int RL = Ends<Tile<F, LGR, true, 1, S_INV_PARITY>, true>::RAD_LAST;
     const uint64_t R = uint64_t(1) << LGR;
     const uint64_t tq = p.out_rows ? (p.out_rows * RL + R - 1) / R : (uint64_t)RL;
+    hipError_t e = hipSuccess;
     switch (p.mode) {
         case S_FWD_BITS: L1(S_FWD_BITS, 0); break;
         case S_FWD: L1(S_FWD, 0); break;
@@ -1146,7 +1182,7 @@ static hipError_t strided_one(const PassLaunch &p, const KArgs &ka0, hipStream_t
             break;
     }
 #undef L1
-    return hipGetLastError();
+    return e;
 }
 
 template <class F, int LGR>
@@ -1157,22 +1193,20 @@ static hipError_t contig_one(const PassLaunch &p, const KArgs &ka, hipStream_t s
         // piece schedules: two pieces over 3*2^30+1, any number over the 64-bit field
         if constexpr (std::is_same<F, FP0>::value || std::is_same<F, FGL>::value) {
             if (p.mode == C_FUSED2)
-                hipLaunchKernelGGL((k_contig<F, LGR, C_FUSED2>), grid, block, 0, s, ka);
+                return launch_k(k_contig<F, LGR, C_FUSED2>, grid, block, 0, s, ka);
             else if (p.mode == C_PROD)
-                hipLaunchKernelGGL((k_contig<F, LGR, C_PROD>), grid, block, 0, s, ka);
+                return launch_k(k_contig<F, LGR, C_PROD>, grid, block, 0, s, ka);
             else if constexpr (std::is_same<F, FGL>::value)
-                hipLaunchKernelGGL((k_contig<F, LGR, C_PROD_ADD>), grid, block, 0, s, ka);
+                return launch_k(k_contig<F, LGR, C_PROD_ADD>, grid, block, 0, s, ka);
             else
                 return hipErrorInvalidValue;
         } else {
             return hipErrorInvalidValue;
         }
     } else if (p.mode == C_FUSED) {
-        hipLaunchKernelGGL((k_contig<F, LGR, C_FUSED>), grid, block, 0, s, ka);
-    } else {
-        hipLaunchKernelGGL((k_contig<F, LGR, C_FWD>), grid, block, 0, s, ka);
+        return launch_k(k_contig<F, LGR, C_FUSED>, grid, block, 0, s, ka);
     }
-    return hipGetLastError();
+    return launch_k(k_contig<F, LGR, C_FWD>, grid, block, 0, s, ka);
 }
 
 constexpr int BB_STRIDED_MAX = 10, BB_CONTIG_MAX = 14, GL_STRIDED_MAX = 10, GL_CONTIG_MAX = 13;
@@ -1318,6 +1352,9 @@ hipError_t launch_contig_p0(const PassLaunch &p, const Tables &t, hipStream_t s)
 #endif
 
 #if NTT_HAS(4)
+thread_local GraphRecorder *t_graph_recorder = nullptr;
+void set_graph_recorder(GraphRecorder *rec) { t_graph_recorder = rec; }
+
 // the 32-bit fields share tile sizes
 int max_strided_lg(int field) { return field == FIELD_GL ? GL_STRIDED_MAX : BB_STRIDED_MAX; }
 int max_contig_lg(int field) { return field == FIELD_GL ? GL_CONTIG_MAX : BB_CONTIG_MAX; }
@@ -1388,8 +1425,7 @@ static hipError_t small_one(uint32_t njobs, const JobDev *jobs, const JobDev *on
     JobDev o;
     if (one) o = *one;
     else std::memset(&o, 0, sizeof(o));
-    hipLaunchKernelGGL((k_small<LG>), dim3(njobs), dim3(SmallTile<LG>::NT), 0, s, jobs, o, t);
-    return hipGetLastError();
+    return launch_k(k_small<LG>, dim3(njobs), dim3(SmallTile<LG>::NT), 0, s, jobs, o, t);
 }
 
 hipError_t launch_small(int lg, uint32_t njobs, const JobDev *jobs, const JobDev *one, const Tables &t,
@@ -1410,9 +1446,9 @@ hipError_t launch_small(int lg, uint32_t njobs, const JobDev *jobs, const JobDev
 
 hipError_t launch_small_batch(const SmallClasses &cls, const JobDev *jobs, uint32_t *counter, unsigned workgroups,
                               const Tables &t, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
-    hipLaunchKernelGGL(k_small_persist, dim3(workgroups), dim3(1024), 0, s, jobs, cls, counter, t);
-    return hipGetLastError();
+    hipError_t e = launch_k(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
+    if (e != hipSuccess) return e;
+    return launch_k(k_small_persist, dim3(workgroups), dim3(1024), 0, s, jobs, cls, counter, t);
 }
 
 hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, const JobDev *one, hipStream_t s) {
@@ -1421,8 +1457,7 @@ hipError_t launch_pack(uint32_t njobs, uint64_t max_words, const JobDev *jobs, c
     else std::memset(&o, 0, sizeof(o));
     unsigned gx = (unsigned)((max_words + 255) / 256);
     if (gx == 0) gx = 1;
-    hipLaunchKernelGGL(k_pack, dim3(gx, njobs), dim3(256), 0, s, jobs, o);
-    return hipGetLastError();
+    return launch_k(k_pack, dim3(gx, njobs), dim3(256), 0, s, jobs, o);
 }
 
 hipError_t launch_embed(uint32_t njobs, uint64_t L, int lgr0, int C, const JobDev *jobs, const JobDev *one,
@@ -1434,13 +1469,9 @@ hipError_t launch_embed(uint32_t njobs, uint64_t L, int lgr0, int C, const JobDe
     if (R % 64 || wpr == 0) return hipErrorInvalidValue;
     const uint64_t row_groups = R / 64, word_groups = (wpr + 15) / 16;
     const dim3 grid((unsigned)(row_groups * word_groups), njobs, degen ? 3 : 2);
-    if (C == 16)
-        hipLaunchKernelGGL((k_embed<16>), grid, dim3(256), 0, s, jobs, o, (uint32_t)lgr0, (uint32_t)row_groups);
-    else if (C == 32)
-        hipLaunchKernelGGL((k_embed<32>), grid, dim3(256), 0, s, jobs, o, (uint32_t)lgr0, (uint32_t)row_groups);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    if (C == 16) return launch_k(k_embed<16>, grid, dim3(256), 0, s, jobs, o, (uint32_t)lgr0, (uint32_t)row_groups);
+    if (C == 32) return launch_k(k_embed<32>, grid, dim3(256), 0, s, jobs, o, (uint32_t)lgr0, (uint32_t)row_groups);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint64_t rows, uint32_t njobs, const JobDev *jobs,
@@ -1452,21 +1483,18 @@ hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint64_t rows, uint3
     rows = (rows == 0 || rows > R) ? R : rows;
     dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((S / C + 63) / 64), njobs);
     if (C == 16) {
-        if (pack) hipLaunchKernelGGL((k_ptrans<16, true>), grid, dim3(256), 0, s, jobs, o, R, S);
-        else hipLaunchKernelGGL((k_ptrans<16, false>), grid, dim3(256), 0, s, jobs, o, R, S);
-    } else {
-        if (pack) hipLaunchKernelGGL((k_ptrans<32, true>), grid, dim3(256), 0, s, jobs, o, R, S);
-        else hipLaunchKernelGGL((k_ptrans<32, false>), grid, dim3(256), 0, s, jobs, o, R, S);
+        if (pack) return launch_k(k_ptrans<16, true>, grid, dim3(256), 0, s, jobs, o, R, S);
+        return launch_k(k_ptrans<16, false>, grid, dim3(256), 0, s, jobs, o, R, S);
     }
-    return hipGetLastError();
+    if (pack) return launch_k(k_ptrans<32, true>, grid, dim3(256), 0, s, jobs, o, R, S);
+    return launch_k(k_ptrans<32, false>, grid, dim3(256), 0, s, jobs, o, R, S);
 }
 
 hipError_t launch_degen(uint32_t njobs, const JobDev *jobs, const JobDev *one, hipStream_t s) {
     JobDev o;
     if (one) o = *one;
     else std::memset(&o, 0, sizeof(o));
-    hipLaunchKernelGGL(k_degen, dim3(njobs), dim3(256), 0, s, jobs, o);
-    return hipGetLastError();
+    return launch_k(k_degen, dim3(njobs), dim3(256), 0, s, jobs, o);
 }
 #endif
 
