@@ -20,6 +20,8 @@ namespace ext {
 //           b'_j = (j < len ? b_j : 0): the input reversed (Circulant: x' = [x, 0],
 //           len = N - 1); a = N for the whole input, a < N for the first piece of
 //           the two-piece schedule (its positions a.. belong to the second piece).
+// The input's map is always PREFIX or REV and the seed's SEED (the
+// single-workgroup path relies on it).
 // Dodis(x, y)_i = XOR_j x_{(j-i) mod n} y_j equals the linear-order Toeplitz
 // extractor of rev(x) with the seed y || y_{0..m-2}: both sides are
 // XOR_{j'} x_{j'} y_{(i+j') mod n}. That needs a transform of length n + m - 1

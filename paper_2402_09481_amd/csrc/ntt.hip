@@ -131,6 +131,31 @@ __host__ __device__ inline uint32_t emb_bit(const Emb &e, uint64_t i, uint64_t L
     return j < e.len ? getbit(e.bits, j) : 0u;
 }
 
+// emb_bit for transforms of at most 2^16 (the single-workgroup path), where
+// every position, length and offset of a job fits 32 bits: the index maps as
+// 32-bit selects rather than branches (jobs side by side in one wave may differ),
+// one load through the global address space per bit. The input's map is PREFIX
+// or REV, the seed's is SEED, as for every job the library builds.
+__device__ inline uint32_t bit_at32(const uint64_t *b, uint32_t idx, bool ok) {
+    idx = ok ? idx : 0u;
+    const uint32_t bit = (uint32_t)(gload(b + (idx >> 6)) >> (idx & 63)) & 1u;
+    return ok ? bit : 0u;
+}
+__device__ inline uint32_t emb_bit32_input(const Emb &e, uint32_t i) {
+    const bool rev = e.mode == EMB_REV;
+    const uint32_t idx = rev ? (uint32_t)e.N - 1u - i : i;
+    return bit_at32(e.bits, idx, (!rev || i < (uint32_t)e.a) && idx < (uint32_t)e.len);
+}
+__device__ inline uint32_t emb_bit32_seed(const Emb &e, uint32_t i, uint32_t L) {
+    uint32_t k = i + (uint32_t)e.a;
+    k = k >= L ? k - L : k;
+    const uint32_t P = (uint32_t)e.P;
+    uint32_t v = k + (uint32_t)e.rot;  // < 3P
+    v = v >= P ? v - P : v;
+    v = v >= P ? v - P : v;
+    return bit_at32(e.bits, v, k < (uint32_t)e.N);
+}
+
 template <int N>
 __host__ __device__ constexpr int bitrev(int i) {
     int r = 0;
@@ -802,23 +827,23 @@ __device__ inline void small_body(const JobDev &J, bool write, uint32_t *lds, ui
     constexpr int RAD0 = Ends<Tl, false>::RAD_FIRST;
     const int lt = Tl::lid();
 
+    static_assert(LG <= 16, "32-bit embedding positions");
+    // both operands' bits are read first, so that the seed's loads are in flight
+    // during the input's transform
     T va[EPT], vb[EPT];
+    const uint32_t L32 = (uint32_t)J.L;
 #pragma unroll
     for (int q = 0; q < EPT / RAD0; ++q) {
         int c, j;
         Tl::template coords<RAD0>(q, c, j);
 #pragma unroll
-        for (int t = 0; t < RAD0; ++t) va[q * RAD0 + t] = emb_bit(J.ex, j + t * (R / RAD0), J.L);
+        for (int t = 0; t < RAD0; ++t) {
+            va[q * RAD0 + t] = emb_bit32_input(J.ex, (uint32_t)(j + t * (R / RAD0)));
+            vb[q * RAD0 + t] = emb_bit32_seed(J.ey, (uint32_t)(j + t * (R / RAD0)), L32);
+        }
     }
     run_steps_from<F, Tl, false, 0>(va, lds, tb);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < EPT / RAD0; ++q) {
-        int c, j;
-        Tl::template coords<RAD0>(q, c, j);
-#pragma unroll
-        for (int t = 0; t < RAD0; ++t) vb[q * RAD0 + t] = emb_bit(J.ey, j + t * (R / RAD0), J.L);
-    }
     run_steps_from<F, Tl, false, 0>(vb, lds, tb);
     const T K = (T)J.K;
 #pragma unroll
