@@ -47,7 +47,7 @@ struct JobDev {
     const void *S2;    // two-piece schedule: the second piece's product spectrum (C_FUSED2 adds it)
     uint64_t *pb;      // packed parity of coefficients [0, out_len) (+1 spare word)
     uint64_t *eb[2];   // the two embedded coefficient vectors as L-bit strings (multi-pass only)
-    uint32_t *flags;   // degenerate check: flags[0] = any one bit, flags[1] = any zero bit
+    uint32_t *flags;   // degenerate check: flags[0] = parts, flags[2 + 2g] / [3 + 2g] = part g saw a one / zero bit
     uint64_t *z;       // caller's output, ceil(m/64) words
     int32_t *status;   // caller's status word or nullptr
     Emb ex, ey;        // embeddings of the input (into A) and the seed (into B)
@@ -180,8 +180,6 @@ hipError_t launch_embed(uint32_t njobs, uint64_t L, int lgr0, int C, const JobDe
 // shapes without the wrap-around fold).
 hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint64_t rows, uint32_t njobs, const JobDev *jobs,
                          const JobDev *one, bool pack, hipStream_t s);
-// Dodis degenerate-input check (writes flags).
-hipError_t launch_degen(uint32_t njobs, const JobDev *jobs, const JobDev *one, hipStream_t s);
 
 // Fixed device workspace of the allocation-free Toeplitz entry point: one array
 // per GPU for the life of the process (ntt.hip). noalloc_scratch_address looks

@@ -975,26 +975,45 @@ __host__ __device__ inline uint64_t embed_word(const Emb &e, uint64_t L, uint64_
     return out;
 }
 
-// Dodis degenerate-input check of one job by one 256-thread workgroup: flags[0] =
-// x has a one bit, flags[1] = x has a zero bit (among its first degen_n bits).
-__device__ inline void degen_body(const JobDev &J) {
+// Dodis degenerate-input check (section "Dodis et al.": x must not be all zeros
+// or all ones), split over the first `parts` (<= DEGEN_PARTS_MAX) workgroups of
+// the embedding's check slice. Part g scans words [g c, (g+1) c) of the first
+// degen_n bits of x (c = ceil(words / parts)) and writes flags[2 + 2g] = the
+// part has a one bit, flags[3 + 2g] = it has a zero bit; part 0 also writes
+// flags[0] = parts. Every part's slots are written on every launch, so the flags
+// need no clearing. degenerate() reduces them (the job's 256-byte flag region
+// holds 64 words).
+constexpr uint32_t DEGEN_PARTS_MAX = 31;
+__device__ inline void degen_part(const JobDev &J, uint32_t g, uint32_t parts) {
     __shared__ uint32_t red[2];
     if (threadIdx.x < 2) red[threadIdx.x] = 0;
     __syncthreads();
-    if (J.degen_n) {
-        const uint64_t nw = (J.degen_n + 63) >> 6;
-        uint32_t one_ = 0, zero_ = 0;
-        for (uint64_t w = threadIdx.x; w < nw; w += 256) {
-            uint64_t x = J.ex.bits[w];
-            uint64_t mk = (w + 1 < nw || (J.degen_n & 63) == 0) ? ~0ull : ((1ull << (J.degen_n & 63)) - 1);
-            one_ |= (x & mk) != 0;
-            zero_ |= (~x & mk) != 0;
-        }
-        if (one_) atomicOr(&red[0], 1u);
-        if (zero_) atomicOr(&red[1], 1u);
+    const uint64_t nw = (J.degen_n + 63) >> 6, chunk = (nw + parts - 1) / parts;
+    const uint64_t w0 = (uint64_t)g * chunk, w1 = umin64(nw, w0 + chunk);
+    const uint64_t tail = (J.degen_n & 63) ? ((1ull << (J.degen_n & 63)) - 1) : ~0ull;
+    uint32_t one_ = 0, zero_ = 0;
+#pragma unroll 4
+    for (uint64_t w = w0 + threadIdx.x; w < w1; w += 256) {
+        const uint64_t x = gload(J.ex.bits + w);
+        const uint64_t mk = w + 1 < nw ? ~0ull : tail;
+        one_ |= (x & mk) != 0;
+        zero_ |= (~x & mk) != 0;
     }
+    if (one_) atomicOr(&red[0], 1u);
+    if (zero_) atomicOr(&red[1], 1u);
     __syncthreads();
-    if (threadIdx.x < 2) J.flags[threadIdx.x] = red[threadIdx.x];
+    if (threadIdx.x < 2) J.flags[2 + 2 * g + threadIdx.x] = red[threadIdx.x];
+    if (g == 0 && threadIdx.x == 0) J.flags[0] = parts;
+}
+__device__ inline bool degenerate(const JobDev &J) {
+    if (!J.degen_n) return false;
+    const uint32_t parts = umin64(J.flags[0], DEGEN_PARTS_MAX);
+    uint32_t one_ = 0, zero_ = 0;
+    for (uint32_t g = 0; g < parts; ++g) {
+        one_ |= J.flags[2 + 2 * g];
+        zero_ |= J.flags[3 + 2 * g];
+    }
+    return one_ == 0 || zero_ == 0;
 }
 
 // The embedded L-bit coefficient strings, in the unit layout the first strided
@@ -1004,14 +1023,15 @@ __device__ inline void degen_body(const JobDev &J) {
 // assembles the words (coalesced along the rows' words) in LDS, then writes each
 // column tile's 64 row units as one contiguous run.
 // blockIdx.z = 0, 1: the embedding of x, y; z = 2 (launched for shapes with the
-// degenerate check): the check, by the first workgroup of the slice.
+// degenerate check): the check, by the slice's first DEGEN_PARTS_MAX workgroups.
 template <int C>
 __global__ void __launch_bounds__(256) k_embed(const JobDev *jobs, JobDev one, uint32_t lgr0, uint32_t row_groups) {
     using Unit = UnitOf<C>;
     constexpr int UPW = 64 / C;  // units per word
     const JobDev &J = jobs ? jobs[blockIdx.y] : one;
     if (blockIdx.z == 2) {
-        if (blockIdx.x == 0) degen_body(J);
+        const uint32_t parts = umin64(gridDim.x, DEGEN_PARTS_MAX);
+        if (blockIdx.x < parts && J.degen_n) degen_part(J, blockIdx.x, parts);
         return;
     }
     __shared__ uint64_t tl[64][17];
@@ -1099,7 +1119,7 @@ __global__ void __launch_bounds__(256) k_pack(const JobDev *jobs, JobDev one) {
     const JobDev &J = jobs ? jobs[blockIdx.y] : one;
     const uint64_t nwm = (J.m + 63) >> 6;
     const uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool degen = J.degen_n && (J.flags[0] == 0 || J.flags[1] == 0);
+    const bool degen = degenerate(J);
     if (w < nwm) {
         uint64_t word = J.pb[w];
         if (J.nfold) {
@@ -1137,7 +1157,7 @@ __global__ void __launch_bounds__(256) k_ptrans(const JobDev *jobs, JobDev one, 
     __syncthreads();
     constexpr int WPR = 64 / UPW;  // words per tile row
     const uint64_t nwm = (J.m + 63) >> 6;
-    const bool degen = PACK && J.degen_n && (J.flags[0] == 0 || J.flags[1] == 0);
+    const bool degen = PACK && degenerate(J);
     for (int idx = threadIdx.x; idx < 64 * WPR; idx += 256) {
         const int rr = idx / WPR, wk = idx % WPR;
         const uint64_t r = r0 + rr, u = u0 + (uint64_t)wk * UPW;
@@ -1160,10 +1180,6 @@ __global__ void __launch_bounds__(256) k_ptrans(const JobDev *jobs, JobDev one, 
     if (PACK && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && J.status) *J.status = degen ? -3 : 0;
 }
 
-__global__ void __launch_bounds__(256) k_degen(const JobDev *jobs, JobDev one) {
-    const JobDev &J = jobs ? jobs[blockIdx.x] : one;
-    degen_body(J);
-}
 
 #endif
 
@@ -1515,12 +1531,6 @@ hipError_t launch_ptrans(int field, uint64_t R, uint64_t S, uint64_t rows, uint3
     return launch_k(k_ptrans<32, false>, grid, dim3(256), 0, s, jobs, o, R, S);
 }
 
-hipError_t launch_degen(uint32_t njobs, const JobDev *jobs, const JobDev *one, hipStream_t s) {
-    JobDev o;
-    if (one) o = *one;
-    else std::memset(&o, 0, sizeof(o));
-    return launch_k(k_degen, dim3(njobs), dim3(256), 0, s, jobs, o);
-}
 #endif
 
 }  // namespace ext
