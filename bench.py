@@ -411,7 +411,7 @@ def run_two_piece(ctx, job, x, y, z, stream, args, single_ms):
             "achieved_GBs": round(total_bytes / (ms * 1e-3) / 1e9, 1), "kernels": kernels}
 
 
-def run_batched(log, count=4096, reps=3, per_block=True):
+def run_batched(log, count=4096, reps=10, per_block=True):
     """The batched workload (4096 Toeplitz/Circulant blocks, n log-uniform in
     [2^10, 2^22], m = n/2): extract_batch (one persistent launch for the
     single-workgroup sizes plus grouped multi-pass launches, replayed from a HIP
@@ -447,7 +447,8 @@ def run_batched(log, count=4096, reps=3, per_block=True):
         return e0.elapsed_time(e1) / n
 
     log("batched: warmup")
-    ctx.batch(dev, sync=True, graph=True)
+    for _ in range(2):
+        ctx.batch(dev, sync=True, graph=True)
     if per_block:
         ctx.batch(dev_u, sync=True, unbatched=True)
     log("batched: timed x%d each" % reps)
@@ -688,7 +689,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget (0 = skip)")
     ap.add_argument("--batched", action="store_true", help="(default) the 4096-block batched comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched comparison")
-    ap.add_argument("--batched-reps", type=int, default=3, help="timed repetitions of each batched form")
+    ap.add_argument("--batched-reps", type=int, default=10,
+                    help="timed back-to-back repetitions of each batched form (the host marshalling of the\n"
+                         "first call is not overlapped with GPU work, so few repetitions overstate the time)")
     ap.add_argument("--no-per-block", action="store_true",
                     help="batched: skip the one-call-per-block comparison (for profiling the batched launches)")
     ap.add_argument("--no-headline", action="store_true",
