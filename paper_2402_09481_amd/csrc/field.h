@@ -33,7 +33,9 @@
 //
 // Besides the values' type T every field names TW, the type of the in-pass
 // (Stockham) twiddle table entries: T itself, or for FLZ the pair w | w' << 32.
-// as_a / as_b prepare a butterfly's first / second operand for add and sub.
+// as_a / as_b prepare a butterfly's first / second operand for add and sub;
+// CONST_PRODUCT_REDUCED says that mul_root and mul_tw already return operands
+// in that form.
 //
 // Every field uses one fixed primitive root of unity w_max of order 2^LGMAX;
 // every transform of length L uses w_L = w_max^(2^LGMAX / L), so that all
@@ -54,6 +56,7 @@ struct FBB {
     static constexpr uint32_t WMAX = 440564289u;   // 31^15: order 2^27 (31 generates the group)
     static constexpr uint32_t R_MOD_P = 268435454u; // 2^32 mod P (Montgomery form of 1)
     static constexpr int WORD_BITS = 32;
+    static constexpr bool CONST_PRODUCT_REDUCED = false;  // see FLZ
 
     __host__ __device__ static constexpr uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
     // a, b in [0, P): result in [0, P). If s >= P, s - P < s; otherwise s - P wraps above s.
@@ -117,6 +120,7 @@ struct FP0 {
     static constexpr uint32_t WMAX = 125u;         // 5^3: order 2^30 (5 generates the group)
     static constexpr uint32_t R_MOD_P = 1073741823u; // 2^32 mod P (Montgomery form of 1)
     static constexpr int WORD_BITS = 32;
+    static constexpr bool CONST_PRODUCT_REDUCED = false;  // see FLZ
 
     // a, b in [0, P): a + b < 2P may carry out of 32 bits; the result is
     // a + b - P when it carried or reached P (no borrow in s - P), else a + b.
@@ -182,6 +186,7 @@ struct FGL {
     // w_RAD^k = 2^(192 k / RAD) for RAD <= 64 (2^96 = -1, so 2 has order 192).
     static constexpr uint64_t WMAX = 5980198667562970375ull;
     static constexpr int WORD_BITS = 64;
+    static constexpr bool CONST_PRODUCT_REDUCED = false;  // see FLZ
 
     // representative in [0, P): subtracting P is adding EPS mod 2^64
     __device__ static inline uint64_t canon(uint64_t a) { return a + (a >= P ? EPS : 0ull); }
@@ -315,6 +320,9 @@ struct FLZ {
     static constexpr uint32_t WMAX = 2187u;       // 3^7: order 2^26 (3 generates the group)
     static constexpr uint32_t R_MOD_P = 67108855u; // 2^32 mod P (Montgomery form of 1)
     static constexpr int WORD_BITS = 32;
+    // the products by known constants (mul_root, mul_tw) return butterfly operands
+    // as they are: their Shoup results lie in [0, 2P), so as_a / as_b are not needed
+    static constexpr bool CONST_PRODUCT_REDUCED = true;
 
     __host__ __device__ static constexpr uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
     // [0, 4P) -> [0, 2P): if v >= 2P, v - 2P < v; otherwise v - 2P wraps above v

@@ -169,39 +169,45 @@ __host__ __device__ constexpr int bitrev(int i) {
 // In-register RAD-point DFT, forward (w_RAD^(t k)) or inverse (w_RAD^-(t k)).
 // Iterative radix-2 decimation in time on bit-reversed input; the roots are
 // compile-time (for the 64-bit field they are powers of 2, applied by shifts).
-template <class F, int RAD, int LEN, int K>
+// TWD: inputs t >= 1 come straight out of the Stockham twiddle product (where
+// the field's constant products return reduced operands, the first layer then
+// prepares only input t = 0, at u[0]).
+template <class F, int RAD, int LEN, int K, bool TWD = false>
 __device__ inline void dft_layer_k(typename F::T *u) {
     if constexpr (K < LEN / 2) {
+        constexpr bool RED_IN = F::CONST_PRODUCT_REDUCED && TWD && LEN == 2;
 #pragma unroll
         for (int s = 0; s < RAD; s += LEN) {
-            typename F::T a = F::as_a(u[s + K]);
+            typename F::T a = (RED_IN && s + K != 0) ? u[s + K] : F::as_a(u[s + K]);
             typename F::T b = u[s + K + LEN / 2];
             if constexpr (K == 0)
-                b = F::as_b(b);
+                b = RED_IN ? b : F::as_b(b);
+            else if constexpr (F::CONST_PRODUCT_REDUCED)
+                b = F::template mul_root<LEN, K>(b);
             else
                 b = F::as_b(F::template mul_root<LEN, K>(b));
             u[s + K] = F::add(a, b);
             u[s + K + LEN / 2] = F::sub(a, b);
         }
-        dft_layer_k<F, RAD, LEN, K + 1>(u);
+        dft_layer_k<F, RAD, LEN, K + 1, TWD>(u);
     }
 }
 
-template <class F, int RAD, int LEN>
+template <class F, int RAD, int LEN, bool TWD = false>
 __device__ inline void dft_layers(typename F::T *u) {
     if constexpr (LEN <= RAD) {
-        dft_layer_k<F, RAD, LEN, 0>(u);
-        dft_layers<F, RAD, LEN * 2>(u);
+        dft_layer_k<F, RAD, LEN, 0, TWD && LEN == 2>(u);
+        dft_layers<F, RAD, LEN * 2, false>(u);
     }
 }
 
-template <class F, int RAD>
+template <class F, int RAD, bool TWD = false>
 __device__ inline void dft_reg(typename F::T *v, bool inv) {
     using T = typename F::T;
     T u[RAD];
 #pragma unroll
     for (int i = 0; i < RAD; ++i) u[bitrev<RAD>(i)] = v[i];
-    dft_layers<F, RAD, 2>(u);
+    dft_layers<F, RAD, 2, TWD>(u);
     // inverse DFT = forward DFT with outputs k and RAD - k exchanged
 #pragma unroll
     for (int k = 0; k < RAD; ++k) v[k] = u[inv ? ((RAD - k) & (RAD - 1)) : k];
@@ -364,7 +370,7 @@ __device__ inline void step_compute(typename F::T *v, const Tables &tb, const ty
 #pragma unroll
             for (int t = 1; t < RAD; ++t) v[q * RAD + t] = F::mul_tw(v[q * RAD + t], tw[(t - 1) * NS + jm]);
         }
-        dft_reg<F, RAD>(&v[q * RAD], INV);
+        dft_reg<F, RAD, (NS > 1)>(&v[q * RAD], INV);
     }
 }
 

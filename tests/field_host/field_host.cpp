@@ -63,6 +63,13 @@ void flz_op(int op, const uint32_t *a, const uint32_t *b, uint32_t *out, size_t 
             case 2: out[i] = FLZ::sub(FLZ::as_a(a[i]), FLZ::as_b(b[i])); break;
             case 3: out[i] = FLZ::canon(a[i]); break;
             case 4: out[i] = FLZ::mul_tw(a[i], FLZ::to_stk(b[i])); break;
+            // butterflies whose second operand is a constant product as it comes
+            // (no as_b: CONST_PRODUCT_REDUCED); the constant is 3^7 (w_max)
+            case 9: out[i] = FLZ::add(FLZ::as_a(a[i]), FLZ::mul_tw(b[i], FLZ::to_stk(FLZ::WMAX))); break;
+            case 10: out[i] = FLZ::sub(FLZ::as_a(a[i]), FLZ::mul_tw(b[i], FLZ::to_stk(FLZ::WMAX))); break;
+            // a first operand that is itself a constant product (no as_a)
+            case 11: out[i] = FLZ::add(FLZ::mul_tw(a[i], FLZ::to_stk(FLZ::WMAX)), FLZ::as_b(b[i])); break;
+            case 12: out[i] = FLZ::sub(FLZ::mul_tw(a[i], FLZ::to_stk(FLZ::WMAX)), FLZ::as_b(b[i])); break;
             case 5: out[i] = lz_root_dispatch<2, 0>(a[i], (int)b[i]); break;
             case 6: out[i] = lz_root_dispatch<4, 0>(a[i], (int)b[i]); break;
             case 7: out[i] = lz_root_dispatch<8, 0>(a[i], (int)b[i]); break;

@@ -164,3 +164,24 @@ def test_lazy_field_shoup_products(lib):
             w = pow(wmax, (1 << 26) // rad * k, PLZ)
             got = lz(lib, op, xs, [k] * len(xs))
             assert all(r % PLZ == xi * w % PLZ and r < 2 * PLZ for xi, r in zip(xs, got)), (rad, k)
+
+
+def test_lazy_field_butterfly_on_unreduced_constant_products(lib):
+    """The lazy field's DFT layers feed the results of products by constants
+    (in-register roots, Stockham twiddles) to the butterfly without reducing them
+    again: those results lie in [0, 2P) for any 32-bit input, so the sum and the
+    difference plus 2P stay in [0, 4P)."""
+    g = np.random.default_rng(23)
+    edge = [0, 1, PLZ - 1, 2 * PLZ - 1, 4 * PLZ - 1, (1 << 32) - 1]
+    a = [x for x in edge for _ in edge] + [int(v) for v in g.integers(0, 4 * PLZ, size=40000)]
+    b = [y for _ in edge for y in edge] + [int(v) for v in g.integers(0, 1 << 32, size=40000, dtype=np.uint64)]
+    w = pow(3, 7, PLZ)
+    a_ok = [x if x < 4 * PLZ else x % (4 * PLZ) for x in a]  # butterfly inputs are lazy values (< 4P)
+    got = lz(lib, 9, a_ok, b)
+    assert all(r % PLZ == (x + y * w) % PLZ and r < 4 * PLZ for x, y, r in zip(a_ok, b, got))
+    got = lz(lib, 10, a_ok, b)
+    assert all(r % PLZ == (x - y * w) % PLZ and r < 4 * PLZ for x, y, r in zip(a_ok, b, got))
+    got = lz(lib, 11, b, a_ok)
+    assert all(r % PLZ == (x * w + y) % PLZ and r < 4 * PLZ for x, y, r in zip(b, a_ok, got))
+    got = lz(lib, 12, b, a_ok)
+    assert all(r % PLZ == (x * w - y) % PLZ and r < 4 * PLZ for x, y, r in zip(b, a_ok, got))
