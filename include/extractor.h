@@ -86,8 +86,10 @@ extern "C" {
  * defines z_i (Toeplitz directly, Dodis and Circulant in their Toeplitz form
  * over the reversed input) split at a = ceil(n/2) rounded up to whole words,
  * each part extracted with its own seed window, the two products added in the
- * transform domain before one inverse — same bits, 32-bit arithmetic. This flag
- * keeps the one transform of nextpow2(n+m-1) over 2^64 - 2^32 + 1.
+ * transform domain before one inverse — same bits, 32-bit arithmetic. In the
+ * same way an extraction whose single transform is 2^27 (over 15*2^27+1) runs
+ * as two pieces over 7*2^26+1 when the halves fit transforms of 2^26. This flag
+ * keeps the one transform of nextpow2(n+m-1) (over 2^64 - 2^32 + 1 beyond 2^30).
  * Shapes longer than one transform of 2^32 (n + m - 1 > 2^32, such as the
  * paper's QRNG example with n = 6.5e9) always run as k pieces over the 64-bit
  * field: the same split into k balanced, word-aligned pieces of input positions,

@@ -154,7 +154,7 @@ class Context:
                 single_transform: bool = False, no_alloc: bool = False) -> "object":
         """cache_seed: keep / reuse the seed's transform (the seed bits at y must not
         change while cached; see seed_cache_clear). single_transform: no two-piece
-        split of large Toeplitz extractions (one transform over the 64-bit field).
+        split (one transform: over the 64-bit field beyond 2^30, over 15*2^27+1 at 2^27).
         no_alloc: Toeplitz through extract_toeplitz_noalloc (the library's fixed
         per-GPU workspace; calls on one GPU must not overlap)."""
         import torch

@@ -578,21 +578,24 @@ int plan_in_field(ext_ctx *c, uint64_t Lmin, int force, Plan &p) {
 
 int plan_for(ext_ctx *c, uint64_t Lmin, Plan &p) { return plan_in_field(c, Lmin, c ? c->force_field : 0, p); }
 
-// Two-piece schedule for shapes beyond one transform of 3*2^30+1. The extraction
+// Two-piece schedule for shapes beyond one transform of 3*2^30+1, and for shapes
+// whose one transform of 2^27 would run over 15*2^27+1 while their pieces fit the
+// lazy field 7*2^26+1 (transforms of at most 2^26). The extraction
 // is a sum over input positions j (Toeplitz: z_i = sum_j s_(i-j+n-1) x_j; Dodis and
 // Circulant: the same with rev(x') and the periodic seed, n the circulant length);
 // it is split at a = ceil(n/2) rounded up to whole words, and each part is a
 // Toeplitz extraction of its a_p input positions with its own seed window of
 // a_p + m - 1 bits, so both run as transforms of length nextpow2(a + m - 1) over
-// 3*2^30+1 (every coefficient of the two convolutions together is at most
-// n < 3*2^30+1). Their products are added in the transform domain before one
-// inverse.
+// 3*2^30+1 or 7*2^26+1 (every coefficient of the two convolutions together is at
+// most n, below either prime where it is used). Their products are added in the
+// transform domain before one inverse.
 constexpr uint64_t TWO_PIECE_MIN_N = 128;
 uint64_t two_piece_split(uint64_t n) { return ((n + 1) / 2 + 63) & ~uint64_t(63); }
 
 // The plan for a shape: a single transform (plan_for), or the two-piece
 // schedule for a shape whose single transform would need the 64-bit field while
-// each piece fits 3*2^30+1 (unless the caller asks for one transform).
+// each piece fits 3*2^30+1, or 15*2^27+1 while each piece fits 7*2^26+1 (unless
+// the caller asks for one transform).
 // Forced-field contexts keep single transforms, except force 4 (testing aid: two
 // pieces whenever n allows).
 // Piece schedule over the 64-bit field, for shapes beyond one transform of 2^32
@@ -640,9 +643,14 @@ int plan_shape(ext_ctx *c, const Shape &s, Plan &p, uint32_t flags = 0) {
         return rc;
     }
     const int rc = plan_for(c, s.Lmin, p);
-    if (rc != EXT_OK || force || p.field != FIELD_GL || !can_split) return rc;
+    if (rc != EXT_OK || force || !can_split) return rc;
+    // one transform over the 64-bit field: two pieces over 3*2^30+1 where the halves
+    // fit; one transform of 2^27 over 15*2^27+1: two pieces of at most 2^26 over the
+    // lazy 7*2^26+1 where the halves fit (fewer values, and cheaper ones)
+    const uint64_t half = two_piece_split(n) + s.m - 1;
+    if (!((p.field == FIELD_GL) || (p.field == FIELD_BB && half <= (uint64_t(1) << FLZ::LGMAX)))) return rc;
     Plan q;
-    if (plan_for(c, two_piece_split(n) + s.m - 1, q) != EXT_OK || q.field != FIELD_P0) return rc;
+    if (plan_for(c, half, q) != EXT_OK || !(q.field == FIELD_P0 || q.field == FIELD_LZ) || q.small) return rc;
     q.pieces = 2;
     q.split = two_piece_split(n);
     p = q;

@@ -750,7 +750,7 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
             for (int t = 0; t < RADL; ++t) {
                 const uint64_t gi = base + (uint64_t)c * R + j + t * (R / RADL);
                 T prod = F::mont(v[q * RADL + t], gload(spec + gi));
-                if constexpr (MODE == C_FUSED2) prod = F::add(prod, F::as_b(gload(prod2 + gi)));
+                if constexpr (MODE == C_FUSED2) prod = F::add(F::as_a(prod), F::as_b(gload(prod2 + gi)));
                 v[q * RADL + t] = prod;
             }
         }
@@ -1237,8 +1237,9 @@ static hipError_t contig_one(const PassLaunch &p, const KArgs &ka, hipStream_t s
     using Tl = Tile<F, LGR, false>;
     dim3 grid((unsigned)p.tiles, p.njobs), block(Tl::NT);
     if (p.mode == C_FUSED2 || p.mode == C_PROD || p.mode == C_PROD_ADD) {
-        // piece schedules: two pieces over 3*2^30+1, any number over the 64-bit field
-        if constexpr (std::is_same<F, FP0>::value || std::is_same<F, FGL>::value) {
+        // piece schedules: two pieces over 3*2^30+1 or 7*2^26+1, any number over
+        // the 64-bit field
+        if constexpr (std::is_same<F, FP0>::value || std::is_same<F, FGL>::value || std::is_same<F, FLZ>::value) {
             if (p.mode == C_FUSED2)
                 return launch_k(k_contig<F, LGR, C_FUSED2>, grid, block, 0, s, ka);
             else if (p.mode == C_PROD)

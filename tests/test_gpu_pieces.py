@@ -10,7 +10,10 @@ QRNG shapes (n = 6.5e9, section "Cryptomite for randomness extraction in
   Circulant, the Dodis degenerate input) against the oracle's whole output;
 * the QRNG Toeplitz and Circulant shapes at their sizes: sampled output words
   against the schoolbook oracle rows, GF(2) bilinearity of the whole output, and
-  the whole output against the same extraction with another piece count."""
+  the whole output against the same extraction with another piece count;
+* shapes whose one transform of 2^27 would run over 15*2^27+1, which the default
+  plan runs as two pieces of at most 2^26 over the lazy field 7*2^26+1: the whole
+  output against the oracle's GF(2)[t] product and against the one transform."""
 import os
 
 import numpy as np
@@ -142,3 +145,39 @@ def test_qrng_circulant_shape():
                 lambda nw: sorted({0, nw // 3, nw - 1, int(W.rng(6).integers(0, nw))}))
     del x, y
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kind,n,m,order", [
+    ("toeplitz", 1 << 26, 1 << 25, "paper"),
+    ("toeplitz", (1 << 26) - 333, (1 << 25) - 7, "linear"),
+    ("dodis", None, 1 << 24, "paper"),        # n: the next prime >= 2^26 - 2^20 with primitive root 2
+    ("circulant", None, (1 << 24) + 5, "paper"),
+])
+def test_two_pieces_over_the_lazy_field(kind, n, m, order):
+    import ctypes
+
+    import paper_2402_09481_amd as P
+    if n is None:
+        p = oracle.next_na((1 << 26) - (1 << 20))
+        n = p if kind == "dodis" else p - 1
+    c = _ctx()
+    wb = ctypes.c_int32()
+    k = {"toeplitz": 0, "circulant": 1, "dodis": 2}[kind]
+    assert c._lib.ext_plan_length(k, n, m, ctypes.byref(wb)) == 1 << 26 and wb.value == 32  # two pieces
+    g = W.rng(n ^ m)
+    x = W.bernoulli_bits(g, n, 0.45)
+    y = W.bernoulli_bits(g, _seed_len(kind, n, m), 0.5)
+    show_case("lazy two-piece", kind, n, m, order)
+    code, z = gpu_extract(c, kind, x, y, n, m, order)
+    assert code == 0
+    want = oracle.extract_product(kind, x, y, n, m, order)[1]
+    assert np.array_equal(z, want)
+    # the one transform of 2^27 over 15*2^27+1 gives the same bits
+    zt = c.extract(kind, to_dev(x), to_dev(y), n, m, seed_order=order, sync=True, single_transform=True)
+    assert np.array_equal(to_host(zt), want)
+    if kind == "dodis":
+        for xd in (np.zeros(W.nwords(n), np.uint64), W.mask_tail(np.full(W.nwords(n), ~np.uint64(0)), n)):
+            code, z = gpu_extract(c, kind, xd, y, n, m)
+            assert code == oracle.EDEGENERATE and not z.any()
+    c.close()
+
