@@ -200,7 +200,9 @@ typedef struct ext_job {
  * grouped launches: jobs are grouped by transform size; all single-workgroup
  * sizes (transform length <= 2^14) run in one persistent launch that takes
  * jobs from a work counter, larger sizes as batched multi-pass launches, one
- * set per size class. With EXT_GRAPH the launch sequence of a batch signature
+ * set per size class. Jobs whose single call would run a piece schedule (see
+ * EXT_SINGLE_TRANSFORM) run it in the batch too, their pieces' launches grouped
+ * like the others'. With EXT_GRAPH the launch sequence of a batch signature
  * is recorded once as a HIP graph and replayed. `jobs` is a host array of
  * `count` entries. Each job is validated on the host first and gets job.err;
  * invalid jobs are skipped (their z untouched). Returns EXT_OK if every job

@@ -1545,24 +1545,29 @@ struct Member {
     Plan plan;
 };
 
+// (a piece schedule's split is per job: it lives in the job's descriptors, so
+// jobs of different splits share launches; the piece count does not)
 std::string plan_key(const Plan &p) {
     char b[64];
-    snprintf(b, sizeof b, "%d:%d:%d:%d.%d.%d.%d", p.field, p.lg, p.small ? 1 : 0, p.lgr[0], p.lgr[1], p.lgr[2],
-             p.lgr[3]);
+    snprintf(b, sizeof b, "%d:%d:%d:%d.%d.%d.%d:%d", p.field, p.lg, p.small ? 1 : 0, p.lgr[0], p.lgr[1], p.lgr[2],
+             p.lgr[3], p.pieces);
     return b;
 }
 
 // Launch layout of a batch: single-workgroup jobs first (sorted by size, one
 // persistent launch), then chunks of one multi-pass size class each. A chunk's
 // jobs get consecutive workspaces; chunks run one after another in stream
-// order and share one workspace region, capped so that a chunk fits it.
+// order and share one workspace region, capped so that a chunk fits it. A chunk
+// of a piece schedule (k pieces) has k descriptors per job: piece q of its
+// jobs at first_desc + q n, in the jobs' order.
 struct BatchLayout {
     std::vector<const Member *> order;
     SmallClasses cls{};
     size_t n_small = 0;
+    size_t ndesc = 0;
     struct Chunk {
         Plan plan;
-        size_t first_desc, n;
+        size_t first_member, first_desc, n;
         uint64_t max_m;
         bool any_degen;
         size_t ws_each;
@@ -1603,6 +1608,7 @@ void layout_batch(ext_ctx *c, const std::vector<Member> &members, BatchLayout &b
     }
     bl.cls.total_items = item;
     bl.order = small;
+    bl.ndesc = small.size();
     const size_t cap = std::max<size_t>(size_t(1) << 30, std::min<size_t>(c->budget / 4, size_t(16) << 30));
     for (auto &kv : large) {
         const Plan &p = kv.second.front()->plan;
@@ -1612,8 +1618,10 @@ void layout_batch(ext_ctx *c, const std::vector<Member> &members, BatchLayout &b
         for (size_t s0 = 0; s0 < kv.second.size(); s0 += per_chunk) {
             BatchLayout::Chunk ch;
             ch.plan = p;
-            ch.first_desc = bl.order.size();
+            ch.first_member = bl.order.size();
+            ch.first_desc = bl.ndesc;
             ch.n = std::min(per_chunk, kv.second.size() - s0);
+            bl.ndesc += ch.n * (size_t)std::max(1, p.pieces);
             ch.max_m = 0;
             ch.any_degen = false;
             ch.ws_each = each;
@@ -1640,12 +1648,13 @@ void fill_descs(const BatchLayout &bl, const ext_job *jobs, char *ws, JobDev *ou
         out[i] = make_jobdev(mb.shape, mb.plan, j.x, j.y, j.z, j.status, j.flags & EXT_SEED_LINEAR, nullptr);
     }
     for (auto &ch : bl.chunks)
-        for (size_t k = 0; k < ch.n; ++k) {
-            const Member &mb = *bl.order[ch.first_desc + k];
-            const ext_job &j = jobs[mb.job];
-            out[ch.first_desc + k] =
-                make_jobdev(mb.shape, mb.plan, j.x, j.y, j.z, j.status, j.flags & EXT_SEED_LINEAR, ws + k * ch.ws_each);
-        }
+        for (int q = 0; q < std::max(1, ch.plan.pieces); ++q)
+            for (size_t k = 0; k < ch.n; ++k) {
+                const Member &mb = *bl.order[ch.first_member + k];
+                const ext_job &j = jobs[mb.job];
+                out[ch.first_desc + (size_t)q * ch.n + k] = make_jobdev(
+                    mb.shape, mb.plan, j.x, j.y, j.z, j.status, j.flags & EXT_SEED_LINEAR, ws + k * ch.ws_each, q);
+            }
 }
 
 hipError_t enqueue_batch(ext_ctx *c, const BatchLayout &bl, JobDev *desc_dev, uint32_t *counter, hipStream_t s,
@@ -1662,8 +1671,20 @@ hipError_t enqueue_batch(ext_ctx *c, const BatchLayout &bl, JobDev *desc_dev, ui
         if (e != hipSuccess) return e;
     }
     for (auto &ch : bl.chunks) {
-        e = enqueue(c, ch.plan, (uint32_t)ch.n, desc_dev + ch.first_desc, nullptr, ch.max_m, ch.any_degen, s,
-                    capturing);
+        const int k = ch.plan.pieces;
+        if (k >= 2) {
+            // the last piece's product, each earlier piece's product plus the sum so
+            // far, then the first piece fused with that sum, one inverse, parity
+            for (int q = k - 1; q >= 1 && e == hipSuccess; --q)
+                e = enqueue(c, ch.plan, (uint32_t)ch.n, desc_dev + ch.first_desc + (size_t)q * ch.n, nullptr, ch.max_m,
+                            false, s, capturing, q == k - 1 ? PH_FWD_BOTH : PH_FWD_ACC);
+            if (e == hipSuccess)
+                e = enqueue(c, ch.plan, (uint32_t)ch.n, desc_dev + ch.first_desc, nullptr, ch.max_m, ch.any_degen, s,
+                            capturing, PH_TWO);
+        } else {
+            e = enqueue(c, ch.plan, (uint32_t)ch.n, desc_dev + ch.first_desc, nullptr, ch.max_m, ch.any_degen, s,
+                        capturing);
+        }
         if (e != hipSuccess) return e;
     }
     return e;
@@ -1752,7 +1773,7 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
         if (rc == EXT_OK && (j.flags & ~(EXT_SEED_LINEAR | EXT_SYNC))) rc = EXT_EINVAL;
         if (rc == EXT_OK && j.kind != EXT_KIND_TOEPLITZ && (j.flags & EXT_SEED_LINEAR)) rc = EXT_EINVAL;
         if (rc == EXT_OK) rc = validate(mb.shape, j.x, j.y, j.z, j.flags & EXT_SEED_LINEAR);
-        if (rc == EXT_OK) rc = plan_for(c, mb.shape.Lmin, mb.plan);
+        if (rc == EXT_OK) rc = plan_shape(c, mb.shape, mb.plan);  // piece schedules included
         j.err = rc;
         if (rc != EXT_OK) {
             if (first == EXT_OK) first = rc;
@@ -1763,7 +1784,7 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
     if (members.empty()) return first;
     BatchLayout bl;
     layout_batch(c, members, bl);
-    const size_t ndesc = bl.order.size();
+    const size_t ndesc = bl.ndesc;
     const size_t desc_bytes = align256(ndesc * sizeof(JobDev));
     hipError_t e = hipSuccess;
     if (flags & EXT_GRAPH) {

@@ -1,6 +1,8 @@
 """Batched extraction: every job of a mixed batch equals the oracle and the same
 job run alone, bit for bit; invalid jobs are reported and skipped; replays of a
-cached batch signature with new inputs stay correct."""
+cached batch signature with new inputs stay correct; jobs that run as piece
+schedules (two pieces over the lazy field at 2^27, two pieces over 3*2^30+1 in a
+context that forces them) are batched with the others."""
 import numpy as np
 import pytest
 
@@ -137,3 +139,57 @@ def test_batched_workload_at_its_sizes():
     c.close()
     del dev
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_with_lazy_two_piece_jobs(ctx, graph):
+    """Jobs whose one transform would be 2^27 run as two pieces over 7*2^26+1 in the
+    batch too (both orders, Dodis with a degenerate input, Circulant), beside
+    single-transform and single-workgroup jobs."""
+    import os
+    big = (1 << 26) - (1 << 20)
+    p = oracle.next_na(big)
+    shapes = [("toeplitz", 1 << 26, 1 << 25, "paper"), ("toeplitz", (1 << 26) - 4097, (1 << 25) - 3, "linear"),
+              ("dodis", p, 1 << 24, "paper"), ("circulant", p - 1, (1 << 24) + 9, "paper"),
+              ("toeplitz", 5000, 2000, "paper"), ("toeplitz", 300000, 150000, "linear"), ("dodis", 65587, 30000, "paper")]
+    jobs = []
+    for i, (kind, n, m, order) in enumerate(shapes):
+        g = W.rng(1000 + i)
+        x = W.bernoulli_bits(g, n, 0.4)
+        if kind == "dodis":
+            x[0] = (int(x[0]) | 1) & ~2
+        y = W.bernoulli_bits(g, {"toeplitz": n + m - 1, "circulant": n + 1, "dodis": n}[kind], 0.5)
+        jobs.append(W.Job(kind, n, m, x, y, order))
+    # a degenerate Dodis input of the two-piece size
+    jobs.append(W.Job("dodis", p, 1 << 24, np.zeros(W.nwords(p), np.uint64), jobs[2].y, "paper"))
+    show_case("batch with lazy two-piece jobs", graph)
+    rc, errs, zs, sts = run_batch(ctx, jobs, graph=graph)
+    assert errs[:-1] == [0] * (len(jobs) - 1)
+    assert sts[-1] == oracle.EDEGENERATE and not zs[-1].any()
+    for j, z, st in zip(jobs[:-1], zs, sts):
+        assert st == 0
+        code, want = oracle.extract_product(j.kind, j.x, j.y, j.n, j.m, j.seed_order)
+        assert code == 0 and np.array_equal(z, want), (j.kind, j.n, j.m)
+
+
+def test_batch_with_forced_two_piece_jobs():
+    """A context that runs every multi-pass shape as two pieces over 3*2^30+1: the
+    batch path's piece descriptors and launch phases at small sizes."""
+    import os
+
+    import paper_2402_09481_amd as P
+    os.environ["EXT_FORCE_FIELD"] = "p0x2"
+    try:
+        c = P.Context(0)
+    finally:
+        del os.environ["EXT_FORCE_FIELD"]
+    jobs = make_batch(48, seed=21, lo=8, hi=16)
+    for graph in (False, True):
+        show_case("forced two-piece batch", graph)
+        rc, errs, zs, sts = run_batch(c, jobs, graph=graph)
+        assert rc == 0 and not any(errs)
+        for j, z, st in zip(jobs, zs, sts):
+            assert st == 0
+            assert np.array_equal(z, oracle.extract(j.kind, j.x, j.y, j.n, j.m, j.seed_order)[1]), (j.kind, j.n, j.m)
+    c.close()
+
