@@ -184,7 +184,7 @@ int extract_von_neumann(ext_ctx *ctx, const uint64_t *x, uint64_t n, uint64_t *z
 
 typedef struct ext_job {
     int32_t kind;          /* EXT_KIND_* */
-    uint32_t flags;        /* EXT_SEED_* (EXT_SYNC is ignored per job) */
+    uint32_t flags;        /* EXT_SEED_*, EXT_SINGLE_TRANSFORM (EXT_SYNC is ignored per job) */
     uint64_t n;            /* input length as for the single calls (Circulant: n_in) */
     uint64_t m;            /* output bits */
     const uint64_t *x;     /* device */

@@ -244,7 +244,7 @@ class Context:
         return int(self._lib.ext_workspace_bytes(KINDS[kind], int(n), int(m)))
 
     def batch(self, jobs, sync: bool = False, stream=None, unbatched: bool = False, graph: bool = False):
-        """jobs: list of dicts with kind, n, m, x, y, z[, seed_order, status]. Returns the
+        """jobs: list of dicts with kind, n, m, x, y, z[, seed_order, status, single_transform]. Returns the
         library's return code and the per-job host validation codes. graph=True captures
         the launch sequence of this batch signature into a HIP graph and replays it."""
         arr = (ExtJob * len(jobs))()
@@ -254,7 +254,8 @@ class Context:
                 raise ValueError("job %d: unknown extractor kind %r" % (i, kind))
             n, m = int(j["n"]), int(j["m"])
             arr[i].kind = KINDS[kind]
-            arr[i].flags = EXT_SEED_LINEAR if j.get("seed_order") == "linear" else 0
+            arr[i].flags = (EXT_SEED_LINEAR if j.get("seed_order") == "linear" else 0) | \
+                (_lib.EXT_SINGLE_TRANSFORM if j.get("single_transform") else 0)
             arr[i].n = n
             arr[i].m = m
             arr[i].x = _ptr(j["x"])

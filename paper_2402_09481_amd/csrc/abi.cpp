@@ -890,10 +890,12 @@ hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs
         if (tr.on) tr.end(pass_label("strided", p.field, pl.lgr, pl.mode, fused));
         if (e != hipSuccess) return e;
     }
-    // the parity transpose writes z itself (the degenerate check ran with the
+    // the 32-bit fields' last inverse pass has written z; for the 64-bit field the
+    // parity transpose writes z itself (the degenerate check ran with the
     // embedding), unless a job folds (z_i = c_i ^ c_(i+n), which reads the packed
     // parity string): batch descriptors never fold
     const bool fold = one && one->nfold;
+    if (!fold && p.field != FIELD_GL) return hipSuccess;
     tr.begin();
     e = launch_ptrans(p.field, uint64_t(1) << p.lgr[0], L >> p.lgr[0], out_rows, njobs, jobs_dev, one, !fold, s);
     if (tr.on) tr.end(fold ? "ptrans" : "ptrans_pack");
@@ -1488,7 +1490,8 @@ int extract_batch_unbatched(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t 
     int first = EXT_OK;
     for (size_t i = 0; i < count; ++i) {
         ext_job &j = jobs[i];
-        j.err = extract_one(ctx, j.kind, j.x, j.n, j.y, j.m, j.z, j.flags & EXT_SEED_LINEAR, j.status,
+        j.err = extract_one(ctx, j.kind, j.x, j.n, j.y, j.m, j.z, j.flags & (EXT_SEED_LINEAR | EXT_SINGLE_TRANSFORM),
+                            j.status,
                             (hipStream_t)stream);
         if (j.err && first == EXT_OK) first = j.err;
     }
@@ -1770,10 +1773,10 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
         Member mb;
         mb.job = i;
         int rc = shape_of(j.kind, j.n, j.m, mb.shape);
-        if (rc == EXT_OK && (j.flags & ~(EXT_SEED_LINEAR | EXT_SYNC))) rc = EXT_EINVAL;
+        if (rc == EXT_OK && (j.flags & ~(EXT_SEED_LINEAR | EXT_SYNC | EXT_SINGLE_TRANSFORM))) rc = EXT_EINVAL;
         if (rc == EXT_OK && j.kind != EXT_KIND_TOEPLITZ && (j.flags & EXT_SEED_LINEAR)) rc = EXT_EINVAL;
         if (rc == EXT_OK) rc = validate(mb.shape, j.x, j.y, j.z, j.flags & EXT_SEED_LINEAR);
-        if (rc == EXT_OK) rc = plan_shape(c, mb.shape, mb.plan);  // piece schedules included
+        if (rc == EXT_OK) rc = plan_shape(c, mb.shape, mb.plan, j.flags);  // piece schedules included
         j.err = rc;
         if (rc != EXT_OK) {
             if (first == EXT_OK) first = rc;

@@ -91,6 +91,21 @@ static hipError_t launch_k(void (*kern)(P...), dim3 grid, dim3 block, size_t shm
 
 // ------------------------------------------------------------------ helpers
 
+// The Dodis degenerate-input check's result, from the flags of its parts (see
+// degen_part): x has no one bit or no zero bit among its first degen_n bits.
+constexpr uint32_t DEGEN_PARTS_MAX = 31;
+__device__ inline bool degenerate(const JobDev &J) {
+    if (!J.degen_n) return false;
+    const uint32_t parts = J.flags[0] < DEGEN_PARTS_MAX ? J.flags[0] : DEGEN_PARTS_MAX;
+    uint32_t one_ = 0, zero_ = 0;
+    for (uint32_t g = 0; g < parts; ++g) {
+        one_ |= J.flags[2 + 2 * g];
+        zero_ |= J.flags[3 + 2 * g];
+    }
+    return one_ == 0 || zero_ == 0;
+}
+
+
 __host__ __device__ inline uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
 // An unsigned integer of C bits (one row segment of a strided tile as bits).
@@ -642,6 +657,13 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
     } else {
         run_steps_from<F, Tl, INV, 0, true>(v, lds, a.tb, stw);
     }
+    // the last inverse pass of the 32-bit fields writes z itself unless the job
+    // folds (z_i = c_i ^ c_(i+n), which needs the whole parity string first)
+    constexpr bool DIRECT = MODE == S_INV_PARITY && C == 32;
+    const bool direct = DIRECT && J.nfold == 0;
+    const uint64_t zbits = DIRECT ? ((J.m + 63) >> 6) << 6 : 0;
+    const bool degen = direct && degenerate(J);
+    if (direct && blockIdx.x == 0 && threadIdx.x == 0 && J.status) *J.status = degen ? -3 : 0;
 #pragma unroll
     for (int q = 0; q < GL; ++q) {
         int c, j;
@@ -668,13 +690,28 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
                 gstore(data + gi, x);
             } else {
                 // level 0 of the inverse: gi is the coefficient index; the C lanes
-                // of a row hold C consecutive coefficients. Their parities go out
-                // tile-major (unit (ct, r) at ct*R + r, contiguous per workgroup);
-                // a transpose kernel turns that into packed natural order.
+                // of a row hold C consecutive coefficients. With 32 columns and no
+                // fold, that row unit's parities go straight into z (bits gi ..
+                // gi + 31, a 32-bit-aligned word of z; bits past m cleared, zero
+                // for a degenerate Dodis input). Otherwise they go out tile-major
+                // (unit (ct, r) at ct*R + r, contiguous per workgroup) and a
+                // transpose kernel turns that into packed natural order.
                 uint32_t bit = (uint32_t)(F::canon(x) & 1u);
                 uint64_t mask = __ballot(bit);
                 const int lane = (int)(threadIdx.x & 63);
-                if (c == 0) gstore((Unit *)J.eb[0] + ct * R + r, (Unit)(mask >> (lane & ~(C - 1))));
+                if (c == 0) {
+                    const Unit u = (Unit)(mask >> (lane & ~(C - 1)));
+                    if (DIRECT && direct) {
+                        if (gi < zbits) {
+                            uint32_t w = (uint32_t)u;
+                            if (degen || gi >= J.m) w = 0u;
+                            else if (J.m - gi < 32) w &= (1u << (uint32_t)(J.m - gi)) - 1u;
+                            gstore((uint32_t *)J.z + (gi >> 5), w);
+                        }
+                    } else {
+                        gstore((Unit *)J.eb[0] + ct * R + r, u);
+                    }
+                }
             }
         }
     }
@@ -989,7 +1026,6 @@ __host__ __device__ inline uint64_t embed_word(const Emb &e, uint64_t L, uint64_
 // flags[0] = parts. Every part's slots are written on every launch, so the flags
 // need no clearing. degenerate() reduces them (the job's 256-byte flag region
 // holds 64 words).
-constexpr uint32_t DEGEN_PARTS_MAX = 31;
 __device__ inline void degen_part(const JobDev &J, uint32_t g, uint32_t parts) {
     __shared__ uint32_t red[2];
     if (threadIdx.x < 2) red[threadIdx.x] = 0;
@@ -1010,16 +1046,6 @@ __device__ inline void degen_part(const JobDev &J, uint32_t g, uint32_t parts) {
     __syncthreads();
     if (threadIdx.x < 2) J.flags[2 + 2 * g + threadIdx.x] = red[threadIdx.x];
     if (g == 0 && threadIdx.x == 0) J.flags[0] = parts;
-}
-__device__ inline bool degenerate(const JobDev &J) {
-    if (!J.degen_n) return false;
-    const uint32_t parts = umin64(J.flags[0], DEGEN_PARTS_MAX);
-    uint32_t one_ = 0, zero_ = 0;
-    for (uint32_t g = 0; g < parts; ++g) {
-        one_ |= J.flags[2 + 2 * g];
-        zero_ |= J.flags[3 + 2 * g];
-    }
-    return one_ == 0 || zero_ == 0;
 }
 
 // The embedded L-bit coefficient strings, in the unit layout the first strided

@@ -55,7 +55,8 @@ def _jobs_for(lg: int, count: int):
         y = torch.randint(-(1 << 62), 1 << 62, ((n + m - 1 + 63) >> 6,), dtype=torch.int64, device="cuda",
                           generator=g)
         z = torch.empty((m + 63) >> 6, dtype=torch.int64, device="cuda")
-        jobs.append({"kind": "toeplitz", "n": n, "m": m, "x": x, "y": y, "z": z})
+        # one transform of the class being tuned (no piece schedule)
+        jobs.append({"kind": "toeplitz", "n": n, "m": m, "x": x, "y": y, "z": z, "single_transform": True})
     return jobs
 
 

@@ -36,14 +36,14 @@ def make_batch(count, seed, lo=6.0, hi=17.0):
     return jobs
 
 
-def run_batch(ctx, jobs, unbatched=False, graph=False):
+def run_batch(ctx, jobs, unbatched=False, graph=False, single_transform=False):
     import torch
     dev = []
     for j in jobs:
         z = torch.full((W.nwords(j.m),), -1, dtype=torch.int64, device="cuda")
         st = torch.full((1,), 777, dtype=torch.int32, device="cuda")
         dev.append({"kind": j.kind, "n": j.n, "m": j.m, "x": to_dev(j.x), "y": to_dev(j.y), "z": z, "status": st,
-                    "seed_order": j.seed_order})
+                    "seed_order": j.seed_order, "single_transform": single_transform})
     rc, errs = ctx.batch(dev, sync=True, unbatched=unbatched, graph=graph)
     torch.cuda.synchronize()
     return rc, errs, [to_host(d["z"]) for d in dev], [int(d["status"].item()) for d in dev]
@@ -170,6 +170,10 @@ def test_batch_with_lazy_two_piece_jobs(ctx, graph):
         assert st == 0
         code, want = oracle.extract_product(j.kind, j.x, j.y, j.n, j.m, j.seed_order)
         assert code == 0 and np.array_equal(z, want), (j.kind, j.n, j.m)
+    # the same batch with one transform per job (EXT_SINGLE_TRANSFORM per job)
+    rc, errs, zs1, sts1 = run_batch(ctx, jobs, graph=graph, single_transform=True)
+    assert rc == 0 and sts1 == sts
+    assert all(np.array_equal(a, b) for a, b in zip(zs, zs1))
 
 
 def test_batch_with_forced_two_piece_jobs():
