@@ -245,7 +245,7 @@ class Context:
 
     def batch(self, jobs, sync: bool = False, stream=None, unbatched: bool = False, graph: bool = False):
         """jobs: list of dicts with kind, n, m, x, y, z[, seed_order, status, single_transform]. Returns the
-        library's return code and the per-job host validation codes. graph=True captures
+        library's return code and the per-job host validation codes. graph=True records
         the launch sequence of this batch signature into a HIP graph and replays it."""
         arr = (ExtJob * len(jobs))()
         for i, j in enumerate(jobs):

@@ -741,7 +741,7 @@ struct Tracer {
     hipStream_t s;
     bool on;
     hipEvent_t a = nullptr;
-    Tracer(ext_ctx *c_, hipStream_t s_, bool capturing) : c(c_), s(s_), on(c_->profile && !capturing) {}
+    Tracer(ext_ctx *c_, hipStream_t s_, bool quiet) : c(c_), s(s_), on(c_->profile && !quiet) {}
     void begin() {
         if (!on) return;
         if (hipEventCreate(&a) != hipSuccess) {
@@ -785,10 +785,14 @@ std::string pass_label(const char *what, int field, int lgr, int mode, int which
 // second piece's product.
 enum Phase { PH_COLD = 0, PH_SEED_ONLY = 1, PH_WARM = 2, PH_FWD_BOTH = 3, PH_TWO = 4, PH_FWD_ACC = 5 };
 
+// The launches of one extraction phase for njobs jobs (descriptors jobs_dev, or
+// the single job `one`). quiet: no tracing events (graph recording and the
+// allocation-free entry point).
+
 hipError_t enqueue(ext_ctx *c, const Plan &p, uint32_t njobs, const JobDev *jobs_dev, const JobDev *one,
-                   uint64_t max_m, bool any_degen, hipStream_t s, bool capturing = false, Phase ph = PH_COLD) {
+                   uint64_t max_m, bool any_degen, hipStream_t s, bool quiet = false, Phase ph = PH_COLD) {
     const Tables &tb = c->tb[p.field];
-    Tracer tr(c, s, capturing);
+    Tracer tr(c, s, quiet);
     if (p.small) {
         tr.begin();
         hipError_t e = launch_small(p.lg, njobs, jobs_dev, one, tb, s);
@@ -1417,7 +1421,7 @@ int extract_toeplitz_noalloc(ext_ctx *c, const uint64_t *x, uint64_t n, const ui
     // every workspace region is written before it is read (embedded bits, both
     // arrays, the parity string), so nothing needs clearing; launches are not
     // traced (tracing creates events)
-    if (enqueue(c, p, 1, nullptr, &jd, sh.m, false, s, /*capturing=*/true) != hipSuccess) return EXT_EDEVICE;
+    if (enqueue(c, p, 1, nullptr, &jd, sh.m, false, s, /*quiet=*/true) != hipSuccess) return EXT_EDEVICE;
     if (!(flags & EXT_SYNC)) return EXT_OK;
     if (hipStreamSynchronize(s) != hipSuccess) return EXT_EDEVICE;
     int32_t v = 0;
@@ -1661,13 +1665,13 @@ void fill_descs(const BatchLayout &bl, const ext_job *jobs, char *ws, JobDev *ou
 }
 
 hipError_t enqueue_batch(ext_ctx *c, const BatchLayout &bl, JobDev *desc_dev, uint32_t *counter, hipStream_t s,
-                         bool capturing) {
+                         bool quiet) {
     hipError_t e = hipSuccess;
     if (bl.cls.total_items) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) cus = 256;
         const unsigned wgs = std::min<unsigned>(bl.cls.total_items, (unsigned)(2 * cus));
-        Tracer tr(c, s, capturing);
+        Tracer tr(c, s, quiet);
         tr.begin();
         e = launch_small_batch(bl.cls, desc_dev, counter, wgs, c->tb[FIELD_LZ], s);
         tr.end("small_persist");
@@ -1680,13 +1684,13 @@ hipError_t enqueue_batch(ext_ctx *c, const BatchLayout &bl, JobDev *desc_dev, ui
             // far, then the first piece fused with that sum, one inverse, parity
             for (int q = k - 1; q >= 1 && e == hipSuccess; --q)
                 e = enqueue(c, ch.plan, (uint32_t)ch.n, desc_dev + ch.first_desc + (size_t)q * ch.n, nullptr, ch.max_m,
-                            false, s, capturing, q == k - 1 ? PH_FWD_BOTH : PH_FWD_ACC);
+                            false, s, quiet, q == k - 1 ? PH_FWD_BOTH : PH_FWD_ACC);
             if (e == hipSuccess)
                 e = enqueue(c, ch.plan, (uint32_t)ch.n, desc_dev + ch.first_desc, nullptr, ch.max_m, ch.any_degen, s,
-                            capturing, PH_TWO);
+                            quiet, PH_TWO);
         } else {
             e = enqueue(c, ch.plan, (uint32_t)ch.n, desc_dev + ch.first_desc, nullptr, ch.max_m, ch.any_degen, s,
-                        capturing);
+                        quiet);
         }
         if (e != hipSuccess) return e;
     }
