@@ -76,7 +76,7 @@ extern "C" {
  * shape (kind, n, m, seed order), so the caller must not change the seed bits
  * at that address while they are cached (ext_seed_cache_clear drops them).
  * A hit skips one of the three transforms. Sizes that run in one workgroup
- * and the two-piece schedule (see EXT_SINGLE_TRANSFORM) ignore the flag. */
+ * and the piece schedules (see EXT_SINGLE_TRANSFORM) ignore the flag. */
 #define EXT_SEED_CACHED 8u
 /* Single calls: compute the extraction as one transform even where the
  * two-piece schedule applies. By default an extraction whose single transform
@@ -223,7 +223,7 @@ int extract_batch_unbatched(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t 
 size_t ext_workspace_bytes(int32_t kind, uint64_t n, uint64_t m);
 
 /* Transform length L and field (32 or 64 = word bits) chosen for a shape by
- * default (for the two-piece schedule: the length of each piece's transforms);
+ * default (for a piece schedule: the length of each piece's transforms);
  * 0 on error. */
 uint64_t ext_plan_length(int32_t kind, uint64_t n, uint64_t m, int32_t *word_bits);
 
