@@ -496,6 +496,10 @@ struct ext_ctx {
     void *tb_mem[NFIELDS][3] = {};
     int force_field = 0;
     uint64_t piece_bits = 0;  // testing aid: piece schedule for every sum longer than this
+    // smallest single transform (log2) replaced by two pieces of half its length, for
+    // single calls and batch members (SPLIT_MIN_LG, BATCH_SPLIT_MIN_LG unless a
+    // testing aid sets them)
+    int split_min_lg = 0, batch_split_min_lg = 0;  // (set by ext_create)
     void *scratch = nullptr;  // this device's allocation-free workspace (noalloc_scratch_address)
     std::map<int, Plan> tuned;  // key: field * 64 + lg
     // pinned status words for EXT_SYNC calls without a status pointer
@@ -628,7 +632,13 @@ int plan_pieces_gl(ext_ctx *c, const Shape &s, uint64_t forced_bits, Plan &p) {
     return EXT_OK;
 }
 
-int plan_shape(ext_ctx *c, const Shape &s, Plan &p, uint32_t flags = 0) {
+// Smallest single transform (log2) that the halving below replaces, for single
+// calls and for batch members, whose extra launches are shared by their class
+// (measured: a single call of 2^25 went 0.48 -> 0.42 ms and one of 2^24 0.23 ->
+// 0.24 ms; the 4096-block batch 54.7 -> 47.7 ms with batch members from 2^17).
+constexpr int SPLIT_MIN_LG = 25, BATCH_SPLIT_MIN_LG = 17;
+
+int plan_shape(ext_ctx *c, const Shape &s, Plan &p, uint32_t flags = 0, bool batch = false) {
     const int force = c ? c->force_field : 0;
     const uint64_t n = conv_n(s);
     const uint64_t piece_bits = c ? c->piece_bits : 0;
@@ -648,7 +658,14 @@ int plan_shape(ext_ctx *c, const Shape &s, Plan &p, uint32_t flags = 0) {
     // fit; one transform of 2^27 over 15*2^27+1: two pieces of at most 2^26 over the
     // lazy 7*2^26+1 where the halves fit (fewer values, and cheaper ones)
     const uint64_t half = two_piece_split(n) + s.m - 1;
-    if (!((p.field == FIELD_GL) || (p.field == FIELD_BB && half <= (uint64_t(1) << FLZ::LGMAX)))) return rc;
+    const bool cheaper_field =
+        p.field == FIELD_GL || (p.field == FIELD_BB && half <= (uint64_t(1) << FLZ::LGMAX));
+    // a single transform that rounds up past twice the halves: two pieces of half
+    // its length, five transforms of L/2 against three of L (a sixth fewer values);
+    // not with a cached seed spectrum, which saves a whole transform of L
+    const int min_lg = batch ? (c ? c->batch_split_min_lg : BATCH_SPLIT_MIN_LG) : (c ? c->split_min_lg : SPLIT_MIN_LG);
+    const bool halving = !(flags & EXT_SEED_CACHED) && !p.small && p.lg >= min_lg && ceil_log2(half) < p.lg;
+    if (!cheaper_field && !halving) return rc;
     Plan q;
     if (plan_for(c, half, q) != EXT_OK || !(q.field == FIELD_P0 || q.field == FIELD_LZ) || q.small) return rc;
     q.pieces = 2;
@@ -1195,6 +1212,11 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
     if (ff && !strcmp(ff, "p0x2")) c->force_field = 4;  // two-piece schedule wherever it can run
     // testing aid: the 64-bit piece schedule with pieces of this many input bits
     if (const char *pb = getenv("EXT_PIECE_BITS")) c->piece_bits = strtoull(pb, nullptr, 10);
+    // testing aids: the transform sizes from which the halving applies
+    c->split_min_lg = SPLIT_MIN_LG;
+    c->batch_split_min_lg = BATCH_SPLIT_MIN_LG;
+    if (const char *v = getenv("EXT_SPLIT_MIN_LG")) c->split_min_lg = atoi(v);
+    if (const char *v = getenv("EXT_BATCH_SPLIT_MIN_LG")) c->batch_split_min_lg = atoi(v);
     // twiddle tables
     auto upload = [&](int f, int k, const void *src, size_t bytes) -> bool {
         void *d = nullptr;
@@ -1780,7 +1802,7 @@ extern "C" int extract_batch(ext_ctx *c, ext_job *jobs, size_t count, uint32_t f
         if (rc == EXT_OK && (j.flags & ~(EXT_SEED_LINEAR | EXT_SYNC | EXT_SINGLE_TRANSFORM))) rc = EXT_EINVAL;
         if (rc == EXT_OK && j.kind != EXT_KIND_TOEPLITZ && (j.flags & EXT_SEED_LINEAR)) rc = EXT_EINVAL;
         if (rc == EXT_OK) rc = validate(mb.shape, j.x, j.y, j.z, j.flags & EXT_SEED_LINEAR);
-        if (rc == EXT_OK) rc = plan_shape(c, mb.shape, mb.plan, j.flags);  // piece schedules included
+        if (rc == EXT_OK) rc = plan_shape(c, mb.shape, mb.plan, j.flags, true);  // piece schedules included
         j.err = rc;
         if (rc != EXT_OK) {
             if (first == EXT_OK) first = rc;

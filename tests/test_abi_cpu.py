@@ -50,10 +50,13 @@ def test_plan_lengths_and_workspace(lib):
     # fit 2^30; shapes whose halves do not keep one transform over the 64-bit field.
     # Likewise a transform of 2^27 (15*2^27+1) becomes two pieces of 2^26 over
     # 7*2^26+1 where the halves fit (n = 2^26, m = 2^25), and stays one transform
-    # where they do not (m = n = 2^26)
+    # where they do not (m = n = 2^26). From 2^25 up, any single transform whose
+    # halves fit half its length runs as two pieces of that half (Toeplitz
+    # n = 2^24, m = 2^23: 2^24 instead of 2^25); below, one transform (Dodis
+    # n = m = 1,048,589 keeps 2^22)
     big_na = lib.ext_next_na(1 << 31)
     cases = [(0, 4096, 2048, 8192, 32), (2, 1048589, 1 << 19, 1 << 21, 32), (0, 1 << 30, 1 << 29, 1 << 30, 32),
-             (1, 1048588, 1000, 1 << 21, 32), (2, 1048589, 1048589, 1 << 22, 32), (0, 1, 1, 64, 32),
+             (1, 1048588, 1000, 1 << 21, 32), (2, 1048589, 1048589, 1 << 22, 32), (0, 1 << 24, 1 << 23, 1 << 24, 32), (0, 1, 1, 64, 32),
              (0, (1 << 26), (1 << 25), 1 << 26, 32), (0, 1 << 26, 1 << 26, 1 << 27, 32),
              (0, 1 << 28, 1 << 28, 1 << 29, 32),
              (2, 1073741827, 1 << 20, 1 << 30, 32), (1, 1738000138, 23998262, 1 << 30, 32),
