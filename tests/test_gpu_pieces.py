@@ -148,6 +148,7 @@ def test_qrng_circulant_shape():
 
 
 @pytest.mark.parametrize("kind,n,m,order", [
+    ("toeplitz", 1 << 24, 1 << 23, "paper"),   # one transform of 2^25 over the lazy field, halved
     ("toeplitz", 1 << 26, 1 << 25, "paper"),
     ("toeplitz", (1 << 26) - 333, (1 << 25) - 7, "linear"),
     ("dodis", None, 1 << 24, "paper"),        # n: the next prime >= 2^26 - 2^20 with primitive root 2
@@ -163,7 +164,8 @@ def test_two_pieces_over_the_lazy_field(kind, n, m, order):
     c = _ctx()
     wb = ctypes.c_int32()
     k = {"toeplitz": 0, "circulant": 1, "dodis": 2}[kind]
-    assert c._lib.ext_plan_length(k, n, m, ctypes.byref(wb)) == 1 << 26 and wb.value == 32  # two pieces
+    L2 = 1 << 24 if n == 1 << 24 else 1 << 26
+    assert c._lib.ext_plan_length(k, n, m, ctypes.byref(wb)) == L2 and wb.value == 32  # two pieces
     g = W.rng(n ^ m)
     x = W.bernoulli_bits(g, n, 0.45)
     y = W.bernoulli_bits(g, _seed_len(kind, n, m), 0.5)
@@ -172,7 +174,7 @@ def test_two_pieces_over_the_lazy_field(kind, n, m, order):
     assert code == 0
     want = oracle.extract_product(kind, x, y, n, m, order)[1]
     assert np.array_equal(z, want)
-    # the one transform of 2^27 over 15*2^27+1 gives the same bits
+    # the one transform (2^27 over 15*2^27+1, or 2^25 over the lazy field) gives the same bits
     zt = c.extract(kind, to_dev(x), to_dev(y), n, m, seed_order=order, sync=True, single_transform=True)
     assert np.array_equal(to_host(zt), want)
     if kind == "dodis":

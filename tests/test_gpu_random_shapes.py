@@ -4,7 +4,8 @@ log-uniformly (m from 1 to its bound, ragged tails, biased inputs), run in the
 default context (single workgroup, lazy field, the lazy two-piece schedule where
 a shape reaches it) and in contexts that force the other fields and schedules
 (15*2^27+1, 3*2^30+1, the 64-bit field, two pieces over 3*2^30+1, the 64-bit
-piece schedule with small pieces). One batch of all the shapes runs as well."""
+piece schedule with small pieces, two pieces of half length from transforms of
+2^15 up). One batch of all the shapes runs as well."""
 import math
 import os
 
@@ -18,17 +19,21 @@ from gpu_helpers import gpu_extract, show_case, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 CONTEXTS = [("default", None, None), ("bb", "bb", None), ("p0", "p0", None), ("gl", "gl", None),
-            ("p0x2", "p0x2", None), ("pieces", None, 2048)]
+            ("p0x2", "p0x2", None), ("pieces", None, 2048), ("halving", None, None)]
 SEEDS = {name: 1000 + i for i, (name, _, _) in enumerate(CONTEXTS)}
 
 
-def _ctx(field, piece_bits):
+def _ctx(field, piece_bits, halving=False):
     import paper_2402_09481_amd as P
-    old = {k: os.environ.get(k) for k in ("EXT_FORCE_FIELD", "EXT_PIECE_BITS")}
+    keys = ("EXT_FORCE_FIELD", "EXT_PIECE_BITS", "EXT_SPLIT_MIN_LG", "EXT_BATCH_SPLIT_MIN_LG")
+    old = {k: os.environ.get(k) for k in keys}
     if field:
         os.environ["EXT_FORCE_FIELD"] = field
     if piece_bits:
         os.environ["EXT_PIECE_BITS"] = str(piece_bits)
+    if halving:  # two pieces of half length wherever the halves fit (single calls and batches)
+        os.environ["EXT_SPLIT_MIN_LG"] = "15"
+        os.environ["EXT_BATCH_SPLIT_MIN_LG"] = "15"
     try:
         return P.Context(0)
     finally:
@@ -69,7 +74,7 @@ def _inputs(kind, n, m, px, s):
 
 @pytest.mark.parametrize("name,field,piece_bits", CONTEXTS)
 def test_random_shapes(name, field, piece_bits):
-    c = _ctx(field, piece_bits)
+    c = _ctx(field, piece_bits, halving=name == "halving")
     lo, hi = (6, 21) if name == "default" else (6, 17)
     count = 40 if name == "default" else 20
     for kind, n, m, order, px, s in _shapes(SEEDS[name], count, lo, hi):
