@@ -294,6 +294,15 @@ __host__ __device__ constexpr int step_twiddle_words(int lgr, int order, bool st
 __host__ __device__ constexpr bool lds_twiddles(bool strided, int cmode) {
     return strided || cmode == C_FWD || cmode == C_PROD || cmode == C_PROD_ADD;
 }
+// The row passes that fuse the product with the transforms around it (C_FUSED,
+// C_FUSED2) take the twiddle blocks of both directions from LDS as well in the
+// lazy field, whose twiddles are Shoup pairs of two registers each: from global
+// memory a step's fifteen pairs are loaded ahead of its butterflies and keep the
+// pass above the register count at which more of its workgroups fit a CU.
+template <class F>
+__host__ __device__ constexpr bool fused_lds_twiddles() {
+    return std::is_same<F, FLZ>::value;
+}
 // SMODE: the pass mode (StridedMode for strided tiles, ContigMode otherwise).
 template <class F, int LGR, bool STRIDED, int ORDER = 1, int SMODE = S_FWD_BITS>
 struct Tile {
@@ -328,10 +337,14 @@ struct Tile {
             if (radix(i, inv) == rad && span(i, inv) == ns) return stw_off(i, inv);
         return 0;
     }
-    static constexpr bool LT = lds_twiddles(STRIDED, SMODE);
-    // (a contiguous tile with LDS twiddles runs the forward direction only)
-    static constexpr int STW_WORDS =
-        !LT ? 0 : STRIDED ? step_twiddle_words(LGR, ORDER, true) : step_twiddle_dir_words(LGR, ORDER, false, false);
+    static constexpr bool FUSED_ROW = !STRIDED && (SMODE == C_FUSED || SMODE == C_FUSED2);
+    static constexpr bool LT = lds_twiddles(STRIDED, SMODE) || (FUSED_ROW && fused_lds_twiddles<F>());
+    // (a contiguous tile with LDS twiddles holds the forward blocks, and the
+    // inverse ones after them if it runs both directions)
+    static constexpr int STW_WORDS = !LT       ? 0
+                                     : STRIDED ? step_twiddle_words(LGR, ORDER, true)
+                                     : FUSED_ROW ? step_twiddle_words(LGR, ORDER, false)
+                                                 : step_twiddle_dir_words(LGR, ORDER, false, false);
     static_assert(!LT || NSTEPS >= 2, "the LDS twiddles are first read after the first step's barrier");
 
     // 64-bit strided tiles exchange values between steps through LDS in two 32-bit
@@ -719,8 +732,26 @@ __attribute__((amdgpu_waves_per_eu(Tile<F, LGR, true, 1, MODE>::WAVES_PER_SIMD))
 
 // ------------------------------------------------------------------ contiguous pass
 
+// Waves per SIMD that the lazy field's row passes promise the register
+// allocator (1: no promise). A workgroup of 2^13 rows puts two waves on each
+// SIMD, so that above 80 registers two of them fit a CU where the LDS admits
+// four; the counts below are the highest each pass reaches without spilling, and
+// each was measured faster on the 4096-block batched workload (the fused passes
+// of 2^13 rows 12-19% faster). The other fields' passes keep the allocator's own
+// choice: the same promises made the two-piece product pass over 3*2^30+1
+// slower.
 template <class F, int LGR, int MODE>
-__global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
+constexpr int contig_waves_per_eu() {
+    if (!std::is_same<F, FLZ>::value) return 1;
+    if ((MODE == C_FUSED || MODE == C_FUSED2) && LGR >= 13) return 6;
+    if (MODE == C_FUSED2 && (LGR == 11 || LGR == 12)) return 5;
+    if (MODE == C_FWD && LGR == 12) return 8;
+    return 1;
+}
+
+template <class F, int LGR, int MODE>
+__global__ void __launch_bounds__((Tile<F, LGR, false>::NT))
+__attribute__((amdgpu_waves_per_eu(contig_waves_per_eu<F, LGR, MODE>()))) k_contig(KArgs a) {
     using Tl = Tile<F, LGR, false, (MODE == C_FWD ? 1 : 2), MODE>;
     using T = typename F::T;
     constexpr int R = Tl::R, C = Tl::C, EPT = Tl::EPT;
@@ -728,16 +759,20 @@ __global__ void __launch_bounds__((Tile<F, LGR, false>::NT)) k_contig(KArgs a) {
     using TW = typename F::TW;
     __shared__ T lds[C * Tl::RP];
     __shared__ TW stw[Tl::STW_WORDS > 0 ? Tl::STW_WORDS : 1];
-    // the small Stockham twiddle blocks of the forward transform, first read in
-    // step 1, after the barrier that follows step 0
+    // the small Stockham twiddle blocks of the forward transform (and of the
+    // inverse one in a fused pass), first read in step 1, after the barrier that
+    // follows step 0
     if constexpr (Tl::LT) {
-        static_assert(!FUSED, "LDS twiddles hold the forward blocks only");
 #pragma unroll
-        for (int s = 1; s < Tl::NSTEPS; ++s) {
-            if (!Tl::stw_local(s, false)) continue;
-            const int rad = Tl::radix(s, false), ns = Tl::span(s, false);
-            const TW *src = (const TW *)a.tb.stk + stk_offset(rad, ns, false);
-            for (int i = threadIdx.x; i < (rad - 1) * ns; i += Tl::NT) stw[Tl::stw_off(s, false) + i] = gload(src + i);
+        for (int d = 0; d < (FUSED ? 2 : 1); ++d) {
+            const bool inv = d == 1;
+#pragma unroll
+            for (int s = 1; s < Tl::NSTEPS; ++s) {
+                if (!Tl::stw_local(s, inv)) continue;
+                const int rad = Tl::radix(s, inv), ns = Tl::span(s, inv);
+                const TW *src = (const TW *)a.tb.stk + stk_offset(rad, ns, inv);
+                for (int i = threadIdx.x; i < (rad - 1) * ns; i += Tl::NT) stw[Tl::stw_off(s, inv) + i] = gload(src + i);
+            }
         }
     }
 
