@@ -245,10 +245,22 @@ int ext_seed_cache_clear(ext_ctx *ctx, size_t *bytes, size_t *entries);
  * lgr[nlev-1] the contiguous one (sum = lg, each within the compiled tile
  * sizes). ext_tune_set overrides the built-in plan for later calls (nlev < 0
  * removes the override); EXT_EINVAL for an unsupported plan. ext_tune_get
- * reports the plan in use. ext_tune_save writes every override as a text line
- * "<word_bits> <lg> <nlev> <lgr...>". */
+ * reports the plan in use. These plans serve batches (extract_batch), and single
+ * calls whose size class has no single-call plan.
+ * ext_tune_set_single / ext_tune_get_single: the plan of single extraction
+ * calls (extract_toeplitz, extract_circulant, extract_dodis and the
+ * allocation-free variant, each piece of a piece schedule included) for one
+ * size class. One job leaves most of the GPU idle, and fewer, larger workgroups
+ * can finish it sooner than the plan that is fastest for many jobs at once.
+ * nlev < 0 removes it (the class falls back to the ext_tune_set plan);
+ * ext_tune_get_single reports the plan a single call uses. ext_tune_save
+ * writes every override as a text line "<word_bits> <lg> <nlev> <lgr...>",
+ * single-call ones as "single <word_bits> <lg> <nlev> <lgr...>"; the tuning
+ * file given to ext_create takes both. */
 int ext_tune_set(ext_ctx *ctx, int word_bits, int lg, int nlev, const int *lgr);
 int ext_tune_get(ext_ctx *ctx, int word_bits, int lg, int *nlev, int *lgr /* 4 entries */);
+int ext_tune_set_single(ext_ctx *ctx, int word_bits, int lg, int nlev, const int *lgr);
+int ext_tune_get_single(ext_ctx *ctx, int word_bits, int lg, int *nlev, int *lgr /* 4 entries */);
 int ext_tune_save(ext_ctx *ctx, const char *path);
 
 /* Primes with 2 as a primitive root (footnote of the Circulant definition;

@@ -216,23 +216,28 @@ class Context:
             m_out = int(m_out.item())
         return (z, m_out) if check else (rc, z, m_out)
 
-    def tune_set(self, word_bits: int, lg: int, levels):
+    def tune_set(self, word_bits: int, lg: int, levels, single: bool = False):
         """Override the plan for transform length 2^lg: levels = [] for one workgroup per
-        job, a list of pass sizes (log2) otherwise, None to drop the override."""
+        job, a list of pass sizes (log2) otherwise, None to drop the override. single:
+        the plan of single extraction calls of that size (ext_tune_set_single) instead of
+        the plan of batches (and of single calls without one of their own)."""
+        fn = self._lib.ext_tune_set_single if single else self._lib.ext_tune_set
         if levels is None:
-            rc = self._lib.ext_tune_set(self.handle, word_bits, lg, -1, None)
+            rc = fn(self.handle, word_bits, lg, -1, None)
         else:
             arr = (ctypes.c_int * 4)(*(list(levels) + [0] * (4 - len(levels))))
-            rc = self._lib.ext_tune_set(self.handle, word_bits, lg, len(levels), arr)
+            rc = fn(self.handle, word_bits, lg, len(levels), arr)
         if rc != EXT_OK:
-            raise ExtError(rc, "ext_tune_set")
+            raise ExtError(rc, "ext_tune_set_single" if single else "ext_tune_set")
 
-    def tune_get(self, word_bits: int, lg: int):
+    def tune_get(self, word_bits: int, lg: int, single: bool = False):
+        """The plan in use for transform length 2^lg (single: the one single calls use)."""
         nlev = ctypes.c_int()
         arr = (ctypes.c_int * 4)()
-        rc = self._lib.ext_tune_get(self.handle, word_bits, lg, ctypes.byref(nlev), arr)
+        fn = self._lib.ext_tune_get_single if single else self._lib.ext_tune_get
+        rc = fn(self.handle, word_bits, lg, ctypes.byref(nlev), arr)
         if rc != EXT_OK:
-            raise ExtError(rc, "ext_tune_get")
+            raise ExtError(rc, "ext_tune_get_single" if single else "ext_tune_get")
         return list(arr[: nlev.value])
 
     def tune_save(self, path: str):

@@ -43,7 +43,8 @@ SYMBOLS = [
     "extract_batch", "extract_batch_unbatched", "ext_workspace_bytes", "ext_plan_length",
     "ext_mem_stats", "ext_trim", "ext_is_na_prime", "ext_next_na", "ext_closest_na",
     "ext_strerror", "ext_version", "ext_profile", "ext_profile_read",
-    "ext_tune_set", "ext_tune_get", "ext_tune_save", "ext_seed_cache_clear", "extract_von_neumann",
+    "ext_tune_set", "ext_tune_get", "ext_tune_set_single", "ext_tune_get_single", "ext_tune_save",
+    "ext_seed_cache_clear", "extract_von_neumann",
     "extract_toeplitz_noalloc",
 ]
 
@@ -121,6 +122,10 @@ def load() -> ctypes.CDLL:
     lib.ext_tune_set.restype = ctypes.c_int
     lib.ext_tune_get.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.ext_tune_get.restype = ctypes.c_int
+    lib.ext_tune_set_single.argtypes = lib.ext_tune_set.argtypes
+    lib.ext_tune_set_single.restype = ctypes.c_int
+    lib.ext_tune_get_single.argtypes = lib.ext_tune_get.argtypes
+    lib.ext_tune_get_single.restype = ctypes.c_int
     lib.ext_tune_save.argtypes = [vp, ctypes.c_char_p]
     lib.ext_tune_save.restype = ctypes.c_int
     lib.ext_seed_cache_clear.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]

@@ -502,6 +502,9 @@ struct ext_ctx {
     int split_min_lg = 0, batch_split_min_lg = 0;  // (set by ext_create)
     void *scratch = nullptr;  // this device's allocation-free workspace (noalloc_scratch_address)
     std::map<int, Plan> tuned;  // key: field * 64 + lg
+    // plans for single extraction calls where they differ (the GPU mostly idle
+    // during one job: fewer, larger workgroups can be faster); same key
+    std::map<int, Plan> tuned_single;
     // pinned status words for EXT_SYNC calls without a status pointer
     std::vector<int32_t *> pinned_status;
     // batch graph cache
@@ -570,17 +573,28 @@ bool valid_plan(const Plan &p) {
 
 // The built-in plan, or the context's tuned one for the same field and length
 // (also in a context that forces a field: a tuned plan of that field applies, so
-// that every plan of every field can be run and checked).
-int plan_in_field(ext_ctx *c, uint64_t Lmin, int force, Plan &p) {
+// that every plan of every field can be run and checked). A single extraction
+// call (single) takes the single-call plan of its size class where there is one.
+int plan_in_field(ext_ctx *c, uint64_t Lmin, int force, Plan &p, bool single = false) {
     int rc = make_plan(Lmin, force, p);
     if (rc != EXT_OK || !c) return rc;
+    const int key = p.field * 64 + p.lg;
     std::lock_guard<std::mutex> g(c->mu);
-    auto it = c->tuned.find(p.field * 64 + p.lg);
+    if (single) {
+        auto it = c->tuned_single.find(key);
+        if (it != c->tuned_single.end()) {
+            p = it->second;
+            return EXT_OK;
+        }
+    }
+    auto it = c->tuned.find(key);
     if (it != c->tuned.end()) p = it->second;
     return EXT_OK;
 }
 
-int plan_for(ext_ctx *c, uint64_t Lmin, Plan &p) { return plan_in_field(c, Lmin, c ? c->force_field : 0, p); }
+int plan_for(ext_ctx *c, uint64_t Lmin, Plan &p, bool single = false) {
+    return plan_in_field(c, Lmin, c ? c->force_field : 0, p, single);
+}
 
 // Two-piece schedule for shapes beyond one transform of 3*2^30+1, and for shapes
 // whose one transform of 2^27 would run over 15*2^27+1 while their pieces fit the
@@ -609,7 +623,7 @@ uint64_t two_piece_split(uint64_t n) { return ((n + 1) / 2 + 63) & ~uint64_t(63)
 // nextpow2(a + m - 1) <= 2^32 (2^31 unless the output leaves pieces under 2^29),
 // the k products added in the transform domain (every coefficient of the whole
 // sum is at most n < 2^64 - 2^32 + 1) before one inverse.
-int plan_pieces_gl(ext_ctx *c, const Shape &s, uint64_t forced_bits, Plan &p) {
+int plan_pieces_gl(ext_ctx *c, const Shape &s, uint64_t forced_bits, Plan &p, bool single) {
     const uint64_t n = conv_n(s);
     uint64_t a;
     if (forced_bits) {
@@ -621,7 +635,7 @@ int plan_pieces_gl(ext_ctx *c, const Shape &s, uint64_t forced_bits, Plan &p) {
         const uint64_t k = (n + amax - 1) / amax;
         a = (((n + k - 1) / k) + 63) & ~uint64_t(63);
     }
-    const int rc = plan_in_field(c, a + s.m - 1, 2, p);
+    const int rc = plan_in_field(c, a + s.m - 1, 2, p, single);
     if (rc != EXT_OK) return rc;
     p.split = a;
     p.pieces = (int)((n + a - 1) / a);
@@ -642,7 +656,7 @@ int plan_shape(ext_ctx *c, const Shape &s, Plan &p, uint32_t flags = 0, bool bat
     const int force = c ? c->force_field : 0;
     const uint64_t n = conv_n(s);
     const uint64_t piece_bits = c ? c->piece_bits : 0;
-    if (s.Lmin > (uint64_t(1) << 32) || (piece_bits && n > piece_bits)) return plan_pieces_gl(c, s, piece_bits, p);
+    if (s.Lmin > (uint64_t(1) << 32) || (piece_bits && n > piece_bits)) return plan_pieces_gl(c, s, piece_bits, p, !batch);
     const bool can_split = !(flags & EXT_SINGLE_TRANSFORM) && n >= TWO_PIECE_MIN_N &&
                            two_piece_split(n) + s.m - 1 <= (uint64_t(1) << FP0::LGMAX);
     if (force == 4) {
@@ -652,7 +666,7 @@ int plan_shape(ext_ctx *c, const Shape &s, Plan &p, uint32_t flags = 0, bool bat
         p.split = two_piece_split(n);
         return rc;
     }
-    const int rc = plan_for(c, s.Lmin, p);
+    const int rc = plan_for(c, s.Lmin, p, !batch);
     if (rc != EXT_OK || force || !can_split) return rc;
     // one transform over the 64-bit field: two pieces over 3*2^30+1 where the halves
     // fit; one transform of 2^27 over 15*2^27+1: two pieces of at most 2^26 over the
@@ -667,7 +681,7 @@ int plan_shape(ext_ctx *c, const Shape &s, Plan &p, uint32_t flags = 0, bool bat
     const bool halving = !(flags & EXT_SEED_CACHED) && !p.small && p.lg >= min_lg && ceil_log2(half) < p.lg;
     if (!cheaper_field && !halving) return rc;
     Plan q;
-    if (plan_for(c, half, q) != EXT_OK || !(q.field == FIELD_P0 || q.field == FIELD_LZ) || q.small) return rc;
+    if (plan_for(c, half, q, !batch) != EXT_OK || !(q.field == FIELD_P0 || q.field == FIELD_LZ) || q.small) return rc;
     q.pieces = 2;
     q.split = two_piece_split(n);
     p = q;
@@ -1265,14 +1279,22 @@ int ext_create(ext_ctx **out, int hip_device, size_t hbm_budget_bytes, const cha
     }
     for (int f = 0; f < NFIELDS; ++f) c->tb[f] = Tables{c->tb_mem[f][0], c->tb_mem[f][1], c->tb_mem[f][2]};
     if (tune_path) {
-        // lines "<word_bits> <lg> <nlev> <lgr...>"; anything unparsable or unsupported is skipped
+        // lines "<word_bits> <lg> <nlev> <lgr...>", and "single <word_bits> <lg> <nlev>
+        // <lgr...>" for single-call plans; anything unparsable or unsupported is skipped
         if (FILE *f = fopen(tune_path, "r")) {
             char line[256];
             while (fgets(line, sizeof line, f)) {
                 if (line[0] == '#') continue;
+                const bool single = strncmp(line, "single ", 7) == 0;
                 int wb, lg, nlev, r[4] = {0, 0, 0, 0};
-                int k = sscanf(line, "%d %d %d %d %d %d %d", &wb, &lg, &nlev, &r[0], &r[1], &r[2], &r[3]);
-                if (k >= 3 && k == 3 + std::max(nlev, 0)) ext_tune_set(c, wb, lg, nlev, r);
+                int k = sscanf(line + (single ? 7 : 0), "%d %d %d %d %d %d %d", &wb, &lg, &nlev, &r[0], &r[1], &r[2],
+                               &r[3]);
+                if (k >= 3 && k == 3 + std::max(nlev, 0)) {
+                    if (single)
+                        ext_tune_set_single(c, wb, lg, nlev, r);
+                    else
+                        ext_tune_set(c, wb, lg, nlev, r);
+                }
             }
             fclose(f);
         }
@@ -1303,13 +1325,16 @@ void ext_destroy(ext_ctx *c) {
     delete c;
 }
 
-int ext_tune_set(ext_ctx *c, int word_bits, int lg, int nlev, const int *lgr) {
+namespace {
+
+int tune_set_in(ext_ctx *c, bool single, int word_bits, int lg, int nlev, const int *lgr) {
     if (!c || (word_bits != 32 && word_bits != 64) || lg < MIN_LG || lg > 32) return EXT_EINVAL;
     const int field = tune_field(word_bits, lg);
     if (field < 0) return EXT_EINVAL;
     std::lock_guard<std::mutex> g(c->mu);
+    std::map<int, Plan> &table = single ? c->tuned_single : c->tuned;
     if (nlev < 0) {
-        c->tuned.erase(field * 64 + lg);
+        table.erase(field * 64 + lg);
         return EXT_OK;
     }
     Plan p;
@@ -1322,19 +1347,24 @@ int ext_tune_set(ext_ctx *c, int word_bits, int lg, int nlev, const int *lgr) {
         p.lgr[i] = lgr[i];
     }
     if (!valid_plan(p)) return EXT_EINVAL;
-    c->tuned[field * 64 + lg] = p;
+    table[field * 64 + lg] = p;
     return EXT_OK;
 }
 
-int ext_tune_get(ext_ctx *c, int word_bits, int lg, int *nlev, int *lgr) {
+int tune_get_in(ext_ctx *c, bool single, int word_bits, int lg, int *nlev, int *lgr) {
     if (!c || (word_bits != 32 && word_bits != 64) || lg < MIN_LG || lg > 32) return EXT_EINVAL;
     const int field = tune_field(word_bits, lg);
     if (field < 0) return EXT_EINVAL;
     Plan p;
     {
         std::lock_guard<std::mutex> g(c->mu);
-        auto it = c->tuned.find(field * 64 + lg);
-        if (it != c->tuned.end()) p = it->second;
+        auto it = single ? c->tuned_single.find(field * 64 + lg) : c->tuned.end();
+        if (!single || it == c->tuned_single.end()) {
+            it = c->tuned.find(field * 64 + lg);
+            if (it != c->tuned.end()) p = it->second;
+        } else {
+            p = it->second;
+        }
     }
     if (p.lg == 0) {
         const int rc = make_plan(uint64_t(1) << lg,
@@ -1347,18 +1377,35 @@ int ext_tune_get(ext_ctx *c, int word_bits, int lg, int *nlev, int *lgr) {
     return EXT_OK;
 }
 
+}  // namespace
+
+int ext_tune_set(ext_ctx *c, int word_bits, int lg, int nlev, const int *lgr) {
+    return tune_set_in(c, false, word_bits, lg, nlev, lgr);
+}
+int ext_tune_get(ext_ctx *c, int word_bits, int lg, int *nlev, int *lgr) {
+    return tune_get_in(c, false, word_bits, lg, nlev, lgr);
+}
+int ext_tune_set_single(ext_ctx *c, int word_bits, int lg, int nlev, const int *lgr) {
+    return tune_set_in(c, true, word_bits, lg, nlev, lgr);
+}
+int ext_tune_get_single(ext_ctx *c, int word_bits, int lg, int *nlev, int *lgr) {
+    return tune_get_in(c, true, word_bits, lg, nlev, lgr);
+}
+
 int ext_tune_save(ext_ctx *c, const char *path) {
     if (!c || !path) return EXT_EINVAL;
     FILE *f = fopen(path, "w");
     if (!f) return EXT_EINVAL;
     std::lock_guard<std::mutex> g(c->mu);
     fprintf(f, "# word_bits lg nlev lgr...  (nlev 0: one workgroup per job)\n");
-    for (auto &kv : c->tuned) {
-        const Plan &p = kv.second;
-        fprintf(f, "%d %d %d", p.field == FIELD_GL ? 64 : 32, p.lg, p.small ? 0 : p.nlev);
-        for (int i = 0; i < (p.small ? 0 : p.nlev); ++i) fprintf(f, " %d", p.lgr[i]);
-        fprintf(f, "\n");
-    }
+    fprintf(f, "# single word_bits lg nlev lgr...  (plans of single extraction calls where they differ)\n");
+    for (int t = 0; t < 2; ++t)
+        for (auto &kv : t ? c->tuned_single : c->tuned) {
+            const Plan &p = kv.second;
+            fprintf(f, "%s%d %d %d", t ? "single " : "", p.field == FIELD_GL ? 64 : 32, p.lg, p.small ? 0 : p.nlev);
+            for (int i = 0; i < (p.small ? 0 : p.nlev); ++i) fprintf(f, " %d", p.lgr[i]);
+            fprintf(f, "\n");
+        }
     fclose(f);
     return EXT_OK;
 }
@@ -1428,7 +1475,7 @@ int extract_toeplitz_noalloc(ext_ctx *c, const uint64_t *x, uint64_t n, const ui
     if (rc) return rc;
     if ((rc = validate(sh, x, y, z, flags)) != EXT_OK) return rc;
     Plan p;
-    if ((rc = plan_for(c, sh.Lmin, p)) != EXT_OK) return rc;
+    if ((rc = plan_for(c, sh.Lmin, p, true)) != EXT_OK) return rc;
     // the last 256 bytes of the scratch hold the status word of EXT_SYNC calls
     // without one of their own
     const size_t status_off = NOALLOC_SCRATCH_BYTES - 256;

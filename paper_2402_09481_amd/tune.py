@@ -8,7 +8,12 @@ file). Timing uses batches of Toeplitz jobs of that class holding at least 2^26
 coefficients, through extract_batch with graph replay, median of a few runs.
 Any plan gives the same bits; only the speed differs.
 
-    python -m paper_2402_09481_amd.tune [--lg 11-27] [--gl] [--out PATH]
+With --single it also times one job per call (back-to-back single extraction
+calls of the class) for every plan, and keeps a single-call plan where one is
+faster than the batch plan by more than SINGLE_MARGIN: one job leaves most of
+the GPU idle, and fewer, larger workgroups can finish it sooner.
+
+    python -m paper_2402_09481_amd.tune [--lg 11-27] [--gl] [--single] [--out PATH]
 """
 from __future__ import annotations
 
@@ -77,7 +82,39 @@ def time_plan(ctx, word_bits, lg, levels, jobs, reps=5):
     return ts[len(ts) // 2]
 
 
-def tune(lgs=range(11, 28), gl=False, out=DEFAULT_TABLE, log=print):
+SINGLE_MARGIN = 0.03
+
+
+def time_single(ctx, word_bits, lg, levels, reps=None):
+    """Milliseconds per call of back-to-back single extractions of the class 2^lg
+    (the shape of _jobs_for), best of three runs."""
+    import torch
+    n = 1 << (lg - 1)
+    m = (1 << (lg - 2)) + 1
+    g = torch.Generator(device="cuda")
+    g.manual_seed(lg)
+    x = torch.randint(-(1 << 62), 1 << 62, ((n + 63) >> 6,), dtype=torch.int64, device="cuda", generator=g)
+    y = torch.randint(-(1 << 62), 1 << 62, ((n + m - 1 + 63) >> 6,), dtype=torch.int64, device="cuda", generator=g)
+    z = torch.empty((m + 63) >> 6, dtype=torch.int64, device="cuda")
+    ctx.tune_set(word_bits, lg, levels, single=True)
+    reps = reps or max(10, min(200, (1 << 27) >> lg))
+    for _ in range(3):
+        ctx.extract("toeplitz", x, y, n, m, z=z, single_transform=True)
+    s = torch.cuda.current_stream()
+    best = None
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            ctx.extract("toeplitz", x, y, n, m, z=z, single_transform=True)
+        e1.record(s)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / reps
+        best = t if best is None else min(best, t)
+    return best
+
+
+def tune(lgs=range(11, 28), gl=False, out=DEFAULT_TABLE, log=print, single=False):
     import torch
 
     import paper_2402_09481_amd as P
@@ -101,6 +138,19 @@ def tune(lgs=range(11, 28), gl=False, out=DEFAULT_TABLE, log=print):
         results.append((wb, lg, best[1], best[0]))
         del jobs
         torch.cuda.empty_cache()
+        if single:
+            times = {}
+            for lv in cands:
+                times[tuple(lv)] = time_single(ctx, wb, lg, lv)
+                log("u%d lg=%d plan=%s  %.1f us per single call" % (wb, lg, lv or "one-workgroup",
+                                                                      times[tuple(lv)] * 1e3))
+            fast = min(times, key=times.get)
+            if list(fast) != best[1] and times[fast] < (1 - SINGLE_MARGIN) * times[tuple(best[1])]:
+                ctx.tune_set(wb, lg, list(fast), single=True)
+                log("single u%d lg=%d %s" % (wb, lg, list(fast)))
+            else:
+                ctx.tune_set(wb, lg, None, single=True)
+            torch.cuda.empty_cache()
     ctx.tune_save(out)
     ctx.close()
     return results
@@ -110,11 +160,13 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--lg", default="11-27")
     ap.add_argument("--gl", action="store_true", help="also tune the 2^31 64-bit plan")
+    ap.add_argument("--single", action="store_true", help="also tune the plans of single calls")
     ap.add_argument("--out", default=DEFAULT_TABLE)
     a = ap.parse_args()
     lo, hi = (int(v) for v in a.lg.split("-"))
     t0 = time.time()
-    for wb, lg, lv, t in tune(range(lo, hi + 1), a.gl, a.out, log=lambda *x: print(*x, flush=True)):
+    for wb, lg, lv, t in tune(range(lo, hi + 1), a.gl, a.out, log=lambda *x: print(*x, flush=True),
+                              single=a.single):
         print("best u%d lg=%d %s %.3f ms" % (wb, lg, lv, t), flush=True)
     print("wrote %s in %.1f s" % (a.out, time.time() - t0), file=sys.stderr)
 

@@ -101,6 +101,8 @@ def test_null_context_calls(lib):
     assert lib.ext_mem_stats(None, None, None, None) == -1
     assert lib.ext_profile(None, 1) == -1
     assert lib.ext_tune_set(None, 32, 20, 2, None) == -1
+    assert lib.ext_tune_set_single(None, 32, 20, 2, None) == -1
+    assert lib.ext_tune_get_single(None, 32, 20, None, None) == -1
 
 
 def test_paper_qrng_shapes_run_as_pieces_of_the_64bit_field(lib):

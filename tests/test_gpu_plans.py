@@ -67,3 +67,70 @@ def test_tune_set_rejects_unsupported():
         with pytest.raises(P.ExtError):
             ctx.tune_set(wb, lg, lv)
     ctx.close()
+
+
+def _labels(ctx, fn):
+    ctx.profile(True)
+    fn()
+    import torch
+    torch.cuda.synchronize()
+    labels = [lab for lab, _ in ctx.profile_read()]
+    ctx.profile(False)
+    return labels
+
+
+@pytest.mark.parametrize("lg,batch_plan,single_plan", [(17, [8, 9], [7, 10]), (21, [9, 12], [8, 13])])
+def test_single_call_plans(lg, batch_plan, single_plan, tmp_path):
+    """A single call takes its size class's single-call plan, a batch the batch plan
+    (seen in the launched kernels' tile sizes), both give the oracle's bits, removing
+    the single-call plan falls back to the batch one, and a saved table restores both."""
+    import torch
+
+    import paper_2402_09481_amd as P
+    ctx = P.Context(0, tune=False)
+    n = (1 << (lg - 1)) - 37
+    m = (1 << (lg - 2)) + 101  # transform length 2^lg
+    g = W.rng(lg + 7)
+    x, y = W.bernoulli_bits(g, n, 0.4), W.bernoulli_bits(g, n + m - 1, 0.5)
+    want = oracle.extract("toeplitz", x, y, n, m)[1]
+    ctx.tune_set(32, lg, batch_plan)
+    ctx.tune_set(32, lg, single_plan, single=True)
+    assert ctx.tune_get(32, lg) == batch_plan and ctx.tune_get(32, lg, single=True) == single_plan
+    contig = lambda labels: sorted({lab for lab in labels if lab.startswith("contig")})
+
+    show_case("single-call plan", lg, single_plan)
+    out = {}
+    labels = _labels(ctx, lambda: out.setdefault("z", gpu_extract(ctx, "toeplitz", x, y, n, m)))
+    code, z = out["z"]
+    assert code == 0 and np.array_equal(z, want)
+    assert contig(labels) and all(("lgr=%d," % single_plan[-1]) in lab for lab in contig(labels)), labels
+
+    show_case("batch plan", lg, batch_plan)
+    from gpu_helpers import to_dev, to_host
+    jobs = [{"kind": "toeplitz", "n": n, "m": m, "x": to_dev(x), "y": to_dev(y), "single_transform": True,
+             "z": torch.full((W.nwords(m),), -1, dtype=torch.int64, device="cuda")} for _ in range(2)]
+    labels = _labels(ctx, lambda: ctx.batch(jobs, sync=True))
+    assert contig(labels) and all(("lgr=%d," % batch_plan[-1]) in lab for lab in contig(labels)), labels
+    for j in jobs:
+        assert np.array_equal(to_host(j["z"]), want)
+
+    path = str(tmp_path / "tune.txt")
+    ctx.tune_save(path)
+    assert any(line.startswith("single 32 %d " % lg) for line in open(path))
+    ctx.tune_set(32, lg, None, single=True)
+    assert ctx.tune_get(32, lg, single=True) == batch_plan
+    ctx.close()
+    ctx2 = P.Context(0, tune=path)
+    assert ctx2.tune_get(32, lg) == batch_plan and ctx2.tune_get(32, lg, single=True) == single_plan
+    ctx2.close()
+
+
+def test_packaged_single_call_plans():
+    """The packaged table's single-call plan for the Dodis workload's transform
+    (2^21) differs from its batch plan."""
+    import paper_2402_09481_amd as P
+    ctx = P.Context(0)
+    assert ctx.tune_get(32, 21) == [9, 12]
+    assert ctx.tune_get(32, 21, single=True) == [8, 13]
+    assert ctx.tune_get(32, 22, single=True) == ctx.tune_get(32, 22)  # no single-call plan of its own
+    ctx.close()
