@@ -10,7 +10,7 @@ from gpu_helpers import show_case, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-TILE_BITS = 1 << 18  # input bits of one workgroup tile (256 threads x 16 words)
+TILE_BITS = 1 << 19  # input bits of one workgroup tile (1024 threads x 8 words)
 SENTINEL = -0x123456789ABCDEF
 
 
@@ -70,7 +70,7 @@ def pattern(kind, n, g):
     raise ValueError(kind)
 
 
-SIZES = [2, 3, 63, 64, 65, 127, 128, 129, 1000, 4097, 65_535,
+SIZES = [2, 3, 63, 64, 65, 127, 128, 129, 1000, 4097, 65_535, TILE_BITS // 2 + 1,
          TILE_BITS - 1, TILE_BITS, TILE_BITS + 1, TILE_BITS + 64, 3 * TILE_BITS + 77, 1_000_003, 4_194_319]
 
 
