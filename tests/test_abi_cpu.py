@@ -126,11 +126,11 @@ def test_paper_qrng_shapes_run_as_pieces_of_the_64bit_field(lib):
 
 
 def test_von_neumann_host_surface(lib):
-    # workspace: look-back state, first and last partial word per tile of 2^18 input bits
+    # workspace: look-back state, first and last partial word per tile of 2^19 input bits
     assert lib.ext_workspace_bytes(3, 1, 0) == 0
     assert lib.ext_workspace_bytes(3, (1 << 40) + 2, 0) == 0
-    tiles = lambda n: -(-((n & ~1) // 64 + (1 if (n & ~1) % 64 else 0)) // 4096)  # noqa: E731
-    for n in (2, 1000, 1 << 18, (1 << 18) + 1, 5 * 10 ** 8, 1 << 33):
+    tiles = lambda n: -(-((n & ~1) // 64 + (1 if (n & ~1) % 64 else 0)) // 8192)  # noqa: E731
+    for n in (2, 1000, 1 << 19, (1 << 19) + 1, 5 * 10 ** 8, 1 << 33):
         want = (3 * 8 * tiles(n) + 256 + 255) // 256 * 256
         assert lib.ext_workspace_bytes(3, n, 0) == want, n
     # the convolution kinds reject nothing they did before; Von Neumann is not a plan
