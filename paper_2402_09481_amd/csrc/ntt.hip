@@ -476,27 +476,30 @@ __device__ inline void exchange_halves(typename F::T *v, typename F::T *lds) {
 
 // Run steps [s0, s1) of a transform whose inputs for step s0 are already in
 // registers; the outputs of step s1-1 stay in registers (positions of the
-// last-step layout if s1 == NSTEPS). LDS exchanges in between.
+// last-step layout if s1 == NSTEPS). LDS exchanges in between. A thread with
+// active = false (uniform in its wave) only takes part in the barriers.
 template <class F, class Tl, bool INV, int S, bool LT = false>
 __device__ inline void run_steps_from(typename F::T *v, typename F::T *lds, const Tables &tb,
-                                      const typename F::TW *stw = nullptr) {
+                                      const typename F::TW *stw = nullptr, bool active = true) {
     if constexpr (S < Tl::NSTEPS) {
         constexpr int RAD = Tl::radix(S, INV);
         constexpr int NS = Tl::span(S, INV);
-        if constexpr (S > 0 && !tile_halfx<Tl>()) {
-            // inputs of this step come from LDS, written by the previous step
-            step_load_lds<F, Tl, RAD>(v, lds);
+        if (active) {
+            if constexpr (S > 0 && !tile_halfx<Tl>()) {
+                // inputs of this step come from LDS, written by the previous step
+                step_load_lds<F, Tl, RAD>(v, lds);
+            }
+            step_compute<F, Tl, RAD, NS, INV, LT>(v, tb, stw);
         }
-        step_compute<F, Tl, RAD, NS, INV, LT>(v, tb, stw);
         if constexpr (S + 1 < Tl::NSTEPS) {
             if constexpr (tile_halfx<Tl>()) {
                 exchange_halves<F, Tl, RAD, NS, Tl::radix(S + 1, INV)>(v, lds);
             } else {
                 __syncthreads();  // every read of the previous layout is done
-                step_store_lds<F, Tl, RAD>(v, lds, NS);
+                if (active) step_store_lds<F, Tl, RAD>(v, lds, NS);
                 __syncthreads();
             }
-            run_steps_from<F, Tl, INV, S + 1, LT>(v, lds, tb, stw);
+            run_steps_from<F, Tl, INV, S + 1, LT>(v, lds, tb, stw, active);
         }
     }
 }
@@ -996,6 +999,110 @@ __global__ void __launch_bounds__(SmallTile<LG>::NT) k_small(const JobDev *jobs,
     __shared__ uint32_t red[2];
     const JobDev &J = jobs ? jobs[blockIdx.x] : one;
     small_body<LG>(J, true, lds, red, tb);
+}
+
+// A single job with its two forward transforms side by side (single calls of
+// 2^10 to 2^13, where the one workgroup is the whole launch): threads [0, NT)
+// transform the input and [NT, 2 NT) the seed, each group in its own tile of
+// LDS_WORDS. The input's group then leaves its spectrum in its tile (positions
+// of the last forward step), the seed's group multiplies by it and runs the
+// inverse in its own tile while the input's group only keeps the barriers, and
+// both groups pack the parity from the seed group's tile. The same arithmetic as
+// small_body, in the same order for each value.
+template <int LG>
+__global__ void __launch_bounds__(2 * SmallTile<LG>::NT) k_small_pair(JobDev J, Tables tb) {
+    using F = FLZ;
+    using Tl = SmallTile<LG>;
+    using T = uint32_t;
+    constexpr int R = Tl::R, EPT = Tl::EPT, NT = Tl::NT, W = Tl::LDS_WORDS;
+    static_assert(NT >= 64 && 2 * NT <= 1024, "groups of whole waves in one workgroup");
+    __shared__ uint32_t lds[2 * W];
+    __shared__ uint32_t red[2];
+    const int g = __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT);  // uniform in a wave
+    uint32_t *const tile = lds + g * W;
+    constexpr int RAD0 = Ends<Tl, false>::RAD_FIRST;
+    constexpr int RADL = Ends<Tl, false>::RAD_LAST;
+    constexpr int RADI = Ends<Tl, true>::RAD_LAST;
+    const uint32_t L32 = (uint32_t)J.L;
+
+    T v[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT / RAD0; ++q) {
+        int c, j;
+        Tl::template coords<RAD0>(q, c, j);
+#pragma unroll
+        for (int t = 0; t < RAD0; ++t) {
+            const uint32_t i = (uint32_t)(j + t * (R / RAD0));
+            v[q * RAD0 + t] = g == 0 ? emb_bit32_input(J.ex, i) : emb_bit32_seed(J.ey, i, L32);
+        }
+    }
+    run_steps_from<F, Tl, false, 0>(v, tile, tb);
+    __syncthreads();  // every read of the tiles by the last forward step is done
+    if (g == 0) {
+#pragma unroll
+        for (int q = 0; q < EPT / RADL; ++q) {
+            int c, j;
+            Tl::template coords<RADL>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RADL; ++t) tile[Tl::lidx(0, j + t * (R / RADL))] = v[q * RADL + t];
+        }
+    }
+    __syncthreads();
+    if (g == 1) {
+        const T K = (T)J.K;
+#pragma unroll
+        for (int q = 0; q < EPT / RADL; ++q) {
+            int c, j;
+            Tl::template coords<RADL>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RADL; ++t) {
+                const T a = lds[Tl::lidx(0, j + t * (R / RADL))];  // the input's tile
+                v[q * RADL + t] = F::mont(F::mont(v[q * RADL + t], a), K);
+            }
+        }
+    }
+    run_steps_from<F, Tl, true, 0>(v, tile, tb, nullptr, g == 1);
+    __syncthreads();
+    if (g == 1) {
+#pragma unroll
+        for (int q = 0; q < EPT / RADI; ++q) {
+            int c, j;
+            Tl::template coords<RADI>(q, c, j);
+#pragma unroll
+            for (int t = 0; t < RADI; ++t) tile[Tl::lidx(0, j + t * (R / RADI))] = F::canon(v[q * RADI + t]);
+        }
+    }
+    if (threadIdx.x < 2) red[threadIdx.x] = 0;
+    __syncthreads();
+    if (J.degen_n) {
+        const uint64_t nw = (J.degen_n + 63) >> 6;
+        uint32_t one_ = 0, zero_ = 0;
+        for (uint64_t w = threadIdx.x; w < nw; w += 2 * NT) {
+            uint64_t x = J.ex.bits[w];
+            uint64_t mk = (w + 1 < nw || (J.degen_n & 63) == 0) ? ~0ull : ((1ull << (J.degen_n & 63)) - 1);
+            one_ |= (x & mk) != 0;
+            zero_ |= (~x & mk) != 0;
+        }
+        if (one_) atomicOr(&red[0], 1u);
+        if (zero_) atomicOr(&red[1], 1u);
+    }
+    __syncthreads();
+    const bool degen = J.degen_n && (red[0] == 0 || red[1] == 0);
+    const uint32_t *const out = lds + W;  // the seed group's tile
+    const uint64_t m = J.m, nfold = J.nfold;
+    const uint64_t nwm = (m + 63) >> 6;
+    const int lane = (int)threadIdx.x & 63;
+    for (uint64_t w = threadIdx.x >> 6; w < nwm; w += 2 * NT / 64) {
+        const uint64_t i = w * 64 + lane;
+        uint32_t bit = 0;
+        if (!degen && i < m) {
+            bit = out[Tl::lidx(0, (int)i)] & 1u;
+            if (nfold) bit ^= out[Tl::lidx(0, (int)(i + nfold))] & 1u;
+        }
+        const uint64_t word = __ballot(bit);
+        if (lane == 0) J.z[w] = word;
+    }
+    if (threadIdx.x == 0 && J.status) *J.status = degen ? -3 : 0;
 }
 
 #if NTT_HAS(4)
@@ -1534,6 +1641,9 @@ static hipError_t small_one(uint32_t njobs, const JobDev *jobs, const JobDev *on
     JobDev o;
     if (one) o = *one;
     else std::memset(&o, 0, sizeof(o));
+    if constexpr (LG >= 10 && LG <= 13) {
+        if (!jobs && one && njobs == 1) return launch_k(k_small_pair<LG>, dim3(1), dim3(2 * SmallTile<LG>::NT), 0, s, o, t);
+    }
     return launch_k(k_small<LG>, dim3(njobs), dim3(SmallTile<LG>::NT), 0, s, jobs, o, t);
 }
 

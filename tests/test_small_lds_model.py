@@ -16,7 +16,11 @@ k_small, lds[2^14 + 2^10] and red[2 * 256] in k_small_persist.
 It also records why a variant that ran the two forward transforms side by side,
 each in its own tile of LDS_WORDS, cannot run in the persistent kernel as it is:
 with the same group offsets its second tile overlaps the next group's tile, and
-the last group's second tile lies past the array."""
+the last group's second tile lies past the array. The single-job kernel that
+does run them side by side (k_small_pair, 2^10 to 2^13: the input's group in
+the first tile of lds[2 LDS_WORDS], the seed's group in the second, the
+input's spectrum handed over through the first tile, packing from the second)
+is modelled the same way."""
 import pytest
 
 LDS_PERSIST = (1 << 14) + (1 << 10)
@@ -94,3 +98,25 @@ def test_two_tiles_per_job_would_overrun_the_persistent_array(lg):
     if jpw > 1:  # overlaps the next group's first tile
         assert second[0][0] == 1 * words
     assert second[-1][1] >= LDS_PERSIST  # the last group's second tile is past the array
+
+
+@pytest.mark.parametrize("lg", range(10, 14))
+def test_pair_kernel_indices_stay_in_their_tiles(lg):
+    R = 1 << lg
+    NT = R // 16
+    words = R + R // 16
+    assert NT >= 64 and 2 * NT <= 1024                  # groups of whole waves in one workgroup
+    per_tile = tile_indices(lg)                         # both groups' steps (a superset for the input's)
+    radl = radices(lg, False)[-1]
+    handover = set()                                    # the input's spectrum, written and read in tile 0
+    for lt in range(NT):
+        for q in range(16 // radl):
+            j = lt + q * NT
+            handover.update(lidx(j + t * (R // radl)) for t in range(radl))
+    assert len(handover) == R and handover <= per_tile
+    packing = {lidx(i) for i in range(R)}               # out[lidx(i)], i < m <= R, in tile 1
+    assert packing <= per_tile
+    for g in (0, 1):
+        absolute = {g * words + i for i in per_tile | (handover if g == 0 else packing)}
+        assert min(absolute) >= g * words and max(absolute) < (g + 1) * words
+    assert 2 * words * 4 <= 160 * 1024                  # lds[2 LDS_WORDS] fits one CU
