@@ -78,9 +78,14 @@ def _status_ptr(status):
     return ctypes.c_void_p(status.data_ptr())
 
 
-def _stream_handle(stream):
+def _stream_handle(stream, device=None):
+    """The HIP stream handle: of `stream` (a torch stream or a raw handle), or torch's
+    current stream on `device` (read without building a stream object)."""
     import torch
     if stream is None:
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None and device is not None:
+            return ctypes.c_void_p(raw(device))
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
@@ -163,7 +168,7 @@ class Context:
         n, m = int(n), int(m)
         if z is None:
             z = torch.empty(words(m), dtype=torch.int64, device=x.device)
-        _ptr(x), _ptr(y), _ptr(z)
+        px, py, pz = _ptr(x), _ptr(y), _ptr(z)
         if 1 <= m <= n <= (1 << 40):  # sizes the library accepts (it rejects the others itself)
             _check_len(x, n, "x")
             _check_len(y, _seed_bits(kind, n, m), "y")
@@ -171,18 +176,17 @@ class Context:
         flags = (EXT_SEED_LINEAR if seed_order == "linear" else 0) | (EXT_SYNC if sync else 0) | \
             (_lib.EXT_SEED_CACHED if cache_seed else 0) | (_lib.EXT_SINGLE_TRANSFORM if single_transform else 0)
         st = _status_ptr(status)
-        s = _stream_handle(stream)
+        s = _stream_handle(stream, self.device)
         if no_alloc:
             if kind != "toeplitz" or cache_seed or single_transform:
                 raise ValueError("no_alloc: Toeplitz only, without cache_seed / single_transform")
-            rc = self._lib.extract_toeplitz_noalloc(self.handle, _ptr(x), int(n), _ptr(y), int(m), _ptr(z), flags,
-                                                    st, s)
+            rc = self._lib.extract_toeplitz_noalloc(self.handle, px, n, py, m, pz, flags, st, s)
         elif kind == "toeplitz":
-            rc = self._lib.extract_toeplitz(self.handle, _ptr(x), int(n), _ptr(y), int(m), _ptr(z), flags, st, s)
+            rc = self._lib.extract_toeplitz(self.handle, px, n, py, m, pz, flags, st, s)
         elif kind == "circulant":
-            rc = self._lib.extract_circulant(self.handle, _ptr(x), int(n), _ptr(y), int(m), _ptr(z), flags, st, s)
+            rc = self._lib.extract_circulant(self.handle, px, n, py, m, pz, flags, st, s)
         elif kind == "dodis":
-            rc = self._lib.extract_dodis(self.handle, _ptr(x), _ptr(y), int(n), int(m), _ptr(z), flags, st, s)
+            rc = self._lib.extract_dodis(self.handle, px, py, n, m, pz, flags, st, s)
         else:
             raise ValueError("unknown extractor kind %r" % kind)
         if check and rc != EXT_OK:
@@ -209,7 +213,7 @@ class Context:
         st = _status_ptr(status)
         rc = self._lib.extract_von_neumann(self.handle, _ptr(x), int(n), _ptr(z), int(z.numel()),
                                            ctypes.c_void_p(m_out.data_ptr()), EXT_SYNC if sync else 0, st,
-                                           _stream_handle(stream))
+                                           _stream_handle(stream, self.device))
         if check and rc != EXT_OK:
             raise ExtError(rc, "extract_von_neumann")
         if sync:
@@ -274,7 +278,7 @@ class Context:
             arr[i].status = st.value if st is not None else None
         fn = self._lib.extract_batch_unbatched if unbatched else self._lib.extract_batch
         flags = (EXT_SYNC if sync else 0) | (_lib.EXT_GRAPH if (graph and not unbatched) else 0)
-        rc = fn(self.handle, arr, len(jobs), flags, _stream_handle(stream))
+        rc = fn(self.handle, arr, len(jobs), flags, _stream_handle(stream, self.device))
         return rc, [arr[i].err for i in range(len(jobs))]
 
 
