@@ -1357,14 +1357,15 @@ int tune_get_in(ext_ctx *c, bool single, int word_bits, int lg, int *nlev, int *
     if (field < 0) return EXT_EINVAL;
     Plan p;
     {
+        // a single call's plan: its own where there is one, else the batch plan
         std::lock_guard<std::mutex> g(c->mu);
-        auto it = single ? c->tuned_single.find(field * 64 + lg) : c->tuned.end();
-        if (!single || it == c->tuned_single.end()) {
-            it = c->tuned.find(field * 64 + lg);
-            if (it != c->tuned.end()) p = it->second;
-        } else {
-            p = it->second;
-        }
+        const int key = field * 64 + lg;
+        auto its = c->tuned_single.find(key);
+        auto itb = c->tuned.find(key);
+        if (single && its != c->tuned_single.end())
+            p = its->second;
+        else if (itb != c->tuned.end())
+            p = itb->second;
     }
     if (p.lg == 0) {
         const int rc = make_plan(uint64_t(1) << lg,
