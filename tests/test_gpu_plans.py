@@ -134,3 +134,24 @@ def test_packaged_single_call_plans():
     assert ctx.tune_get(32, 21, single=True) == [8, 13]
     assert ctx.tune_get(32, 22, single=True) == ctx.tune_get(32, 22)  # no single-call plan of its own
     ctx.close()
+
+
+def test_tuner_single_mode(tmp_path):
+    """The tuner's --single mode on one size class: it writes the batch plan, and a
+    single-call plan only if that plan is one of the candidates and differs from the
+    batch plan; the written table loads into a context."""
+    import paper_2402_09481_amd as P
+    from paper_2402_09481_amd.tune import candidates, tune
+    out = str(tmp_path / "t.txt")
+    res = tune(range(17, 18), out=out, log=lambda *a: None, single=True)
+    assert len(res) == 1 and res[0][:2] == (32, 17)
+    lines = [ln.split() for ln in open(out) if not ln.startswith("#")]
+    batch = [list(map(int, ln[3:])) for ln in lines if ln[0] == "32" and ln[1] == "17"]
+    single = [list(map(int, ln[4:])) for ln in lines if ln[0] == "single" and ln[2] == "17"]
+    assert batch == [res[0][2]]
+    cands = candidates(32, 17)
+    assert all(s in cands and s != batch[0] for s in single)
+    ctx = P.Context(0, tune=out)
+    assert ctx.tune_get(32, 17) == batch[0]
+    assert ctx.tune_get(32, 17, single=True) == (single[0] if single else batch[0])
+    ctx.close()
