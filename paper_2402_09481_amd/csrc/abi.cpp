@@ -972,9 +972,12 @@ void seed_free(ext_ctx::SeedEntry &se) {
 // runs the cold path.
 ext_ctx::SeedEntry *seed_entry(ext_ctx *c, const Shape &sh, const Plan &p, const uint64_t *y, uint32_t flags,
                                hipStream_t s, const JobDev &jd, hipError_t &e) {
-    char key[160];
-    snprintf(key, sizeof key, "%p:%d:%llu:%llu:%u:%d:%d", (const void *)y, sh.kind, (unsigned long long)sh.n,
-             (unsigned long long)sh.m, flags & EXT_SEED_LINEAR, p.field, p.lg);
+    // (the pass split is part of the key: the spectrum's order in memory follows
+    // the plan, and the plan of a size class can change between calls)
+    char key[192];
+    snprintf(key, sizeof key, "%p:%d:%llu:%llu:%u:%d:%d:%d.%d.%d.%d.%d", (const void *)y, sh.kind,
+             (unsigned long long)sh.n, (unsigned long long)sh.m, flags & EXT_SEED_LINEAR, p.field, p.lg, p.nlev,
+             p.lgr[0], p.lgr[1], p.lgr[2], p.lgr[3]);
     const size_t bytes = (size_t(1) << p.lg) * (p.field == FIELD_GL ? 8 : 4);
     std::unique_lock<std::mutex> g(c->mu);
     auto it = c->seeds.find(key);

@@ -73,3 +73,21 @@ def test_cached_seed_64bit_field():
     check(c, "toeplitz", 50000, 20000, seed=5)
     check(c, "dodis", 8219, 8219, seed=6)
     c.close()
+
+
+def test_plan_change_between_cached_calls():
+    """A seed spectrum cached under one plan of its size class is not reused after
+    the class's plan changes (the spectrum's order in memory follows the plan)."""
+    import paper_2402_09481_amd as P
+    c = P.Context(0, tune=False)
+    n, m = 70001, 30000  # transform 2^17
+    g = W.rng(11)
+    y = W.bernoulli_bits(g, n + m - 1, 0.5)
+    yd = to_dev(y)
+    for plan in ([8, 9], [7, 10], [9, 8], [8, 9]):
+        c.tune_set(32, 17, plan, single=True)
+        x = W.bernoulli_bits(g, n, 0.4)
+        show_case("seed cache under plan", plan)
+        z = c.extract("toeplitz", to_dev(x), yd, n, m, sync=True, cache_seed=True)
+        assert np.array_equal(to_host(z), oracle.extract("toeplitz", x, y, n, m)[1]), plan
+    c.close()
