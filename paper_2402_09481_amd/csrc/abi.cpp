@@ -537,6 +537,7 @@ struct ext_ctx {
         hipEvent_t used = nullptr;   // the last call that read it is complete
         uint64_t tick = 0;
         int busy = 0;                // calls between lookup and recording `used`
+        bool recorded = false;       // `ready` is recorded (before that, other calls must not wait on it)
     };
     std::map<std::string, SeedEntry> seeds;
     size_t seed_bytes = 0;
@@ -982,6 +983,9 @@ ext_ctx::SeedEntry *seed_entry(ext_ctx *c, const Shape &sh, const Plan &p, const
     std::unique_lock<std::mutex> g(c->mu);
     auto it = c->seeds.find(key);
     if (it != c->seeds.end()) {
+        // an entry whose transform another call is still enqueueing: waiting on
+        // its unrecorded event would not wait, so this call runs without the cache
+        if (!it->second.recorded) return nullptr;
         it->second.tick = ++c->seed_tick;
         it->second.busy++;
         ext_ctx::SeedEntry *se = &it->second;
@@ -1024,6 +1028,10 @@ ext_ctx::SeedEntry *seed_entry(ext_ctx *c, const Shape &sh, const Plan &p, const
     e = enqueue(c, p, 1, nullptr, &sj, sh.m, false, s, false, PH_SEED_ONLY);
     if (e == hipSuccess) e = hipEventRecord(ent->ready, s);
     if (e == hipSuccess) e = hipEventRecord(ent->used, s);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> g2(c->mu);
+        ent->recorded = true;
+    }
     return ent;
 }
 

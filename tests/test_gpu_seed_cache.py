@@ -91,3 +91,46 @@ def test_plan_change_between_cached_calls():
         z = c.extract("toeplitz", to_dev(x), yd, n, m, sync=True, cache_seed=True)
         assert np.array_equal(to_host(z), oracle.extract("toeplitz", x, y, n, m)[1]), plan
     c.close()
+
+
+def test_cached_seed_from_several_threads():
+    """Calls from four host threads, each on its own stream, that share one cached
+    seed: a call that finds the entry while another is still enqueueing its
+    transform runs without the cache; every result equals the oracle."""
+    import threading
+
+    import torch
+
+    import paper_2402_09481_amd as P
+    c = P.Context(0)
+    n, m = 300007, 100003
+    g = W.rng(21)
+    y = W.bernoulli_bits(g, n + m - 1, 0.5)
+    xs = [[W.bernoulli_bits(g, n, 0.4) for _ in range(6)] for _ in range(4)]
+    wants = [[oracle.extract("toeplitz", x, y, n, m)[1] for x in row] for row in xs]
+    yd = to_dev(y)
+    for rep in range(3):
+        c.seed_cache_clear()
+        errors = []
+
+        def worker(t):
+            try:
+                s = torch.cuda.Stream()
+                xd = [to_dev(x) for x in xs[t]]
+                torch.cuda.synchronize()
+                for k, x in enumerate(xd):
+                    z = c.extract("toeplitz", x, yd, n, m, sync=True, stream=s, cache_seed=True)
+                    if not np.array_equal(to_host(z), wants[t][k]):
+                        errors.append((rep, t, k))
+            except Exception as e:  # reported by the main thread
+                errors.append((rep, t, repr(e)))
+
+        show_case("seed cache threads", rep)
+        th = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        torch.cuda.synchronize()
+        assert not errors, errors[:4]
+    c.close()
