@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -541,6 +542,7 @@ struct ext_ctx {
     };
     std::map<std::string, SeedEntry> seeds;
     size_t seed_bytes = 0;
+    int seed_clearing = 0;  // clears in progress: calls run without the cache meanwhile
     uint64_t seed_tick = 0;
     // tracing
     bool profile = false;
@@ -981,6 +983,7 @@ ext_ctx::SeedEntry *seed_entry(ext_ctx *c, const Shape &sh, const Plan &p, const
              p.lgr[0], p.lgr[1], p.lgr[2], p.lgr[3]);
     const size_t bytes = (size_t(1) << p.lg) * (p.field == FIELD_GL ? 8 : 4);
     std::unique_lock<std::mutex> g(c->mu);
+    if (c->seed_clearing) return nullptr;
     auto it = c->seeds.find(key);
     if (it != c->seeds.end()) {
         // an entry whose transform another call is still enqueueing: waiting on
@@ -1424,7 +1427,20 @@ int ext_tune_save(ext_ctx *c, const char *path) {
 
 int ext_seed_cache_clear(ext_ctx *c, size_t *bytes, size_t *entries) {
     if (!c) return EXT_EINVAL;
-    std::lock_guard<std::mutex> g(c->mu);
+    std::unique_lock<std::mutex> g(c->mu);
+    // new calls run without the cache until the clear is done; calls that hold an
+    // entry (between its lookup and the event that marks their last read of it)
+    // finish with it first
+    ++c->seed_clearing;
+    for (;;) {
+        bool busy = false;
+        for (auto &kv : c->seeds) busy |= kv.second.busy > 0;
+        if (!busy) break;
+        g.unlock();
+        std::this_thread::yield();
+        g.lock();
+    }
+    --c->seed_clearing;
     if (bytes) *bytes = c->seed_bytes;
     if (entries) *entries = c->seeds.size();
     for (auto &kv : c->seeds) seed_free(kv.second);

@@ -95,8 +95,11 @@ def test_plan_change_between_cached_calls():
 
 def test_cached_seed_from_several_threads():
     """Calls from four host threads, each on its own stream, that share one cached
-    seed: a call that finds the entry while another is still enqueueing its
-    transform runs without the cache; every result equals the oracle."""
+    seed (and, from the second repetition on, a fifth thread clearing the cache
+    all the while): a call that finds the entry while another is still
+    enqueueing its transform, or while a clear is under way, runs without the
+    cache; a clear waits for calls that hold an entry; every result equals the
+    oracle."""
     import threading
 
     import torch
@@ -125,12 +128,22 @@ def test_cached_seed_from_several_threads():
             except Exception as e:  # reported by the main thread
                 errors.append((rep, t, repr(e)))
 
+        stop = threading.Event()
+
+        def clearer():  # from the second repetition on, the cache is cleared while calls use it
+            while rep > 0 and not stop.is_set():
+                c.seed_cache_clear()
+
         show_case("seed cache threads", rep)
         th = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+        cl = threading.Thread(target=clearer)
+        cl.start()
         for t in th:
             t.start()
         for t in th:
             t.join()
+        stop.set()
+        cl.join()
         torch.cuda.synchronize()
         assert not errors, errors[:4]
     c.close()
