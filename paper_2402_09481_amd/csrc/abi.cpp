@@ -1591,9 +1591,13 @@ int extract_batch_unbatched(ext_ctx *ctx, ext_job *jobs, size_t count, uint32_t 
     int first = EXT_OK;
     for (size_t i = 0; i < count; ++i) {
         ext_job &j = jobs[i];
-        j.err = extract_one(ctx, j.kind, j.x, j.n, j.y, j.m, j.z, j.flags & (EXT_SEED_LINEAR | EXT_SINGLE_TRANSFORM),
-                            j.status,
-                            (hipStream_t)stream);
+        // the job checks of extract_batch (the seed order is a Toeplitz option)
+        if ((j.flags & ~(EXT_SEED_LINEAR | EXT_SYNC | EXT_SINGLE_TRANSFORM)) ||
+            (j.kind != EXT_KIND_TOEPLITZ && (j.flags & EXT_SEED_LINEAR)))
+            j.err = EXT_EINVAL;
+        else
+            j.err = extract_one(ctx, j.kind, j.x, j.n, j.y, j.m, j.z, j.flags & (EXT_SEED_LINEAR | EXT_SINGLE_TRANSFORM),
+                                j.status, (hipStream_t)stream);
         if (j.err && first == EXT_OK) first = j.err;
     }
     if ((flags & EXT_SYNC) && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return EXT_EDEVICE;

@@ -100,6 +100,26 @@ def test_batch_reports_invalid_jobs(ctx):
         assert np.array_equal(zs[i], oracle.extract(j.kind, j.x, j.y, j.n, j.m, j.seed_order)[1])
 
 
+@pytest.mark.parametrize("unbatched", [False, True])
+def test_linear_seed_order_is_a_toeplitz_option(ctx, unbatched):
+    """A Circulant or Dodis job that asks for the linear seed order is rejected
+    (EXT_EINVAL, as by extract_circulant / extract_dodis) in the batch and in the
+    per-job comparison alike; the other jobs run."""
+    jobs = make_batch(6, seed=31, lo=8, hi=12)
+    na = oracle.next_na(200)
+    circ = W.make_job("circulant", na - 1, 50, 0.4, 4, seed_order="linear")
+    dod = W.make_job("dodis", na, 60, 0.4, 5, seed_order="linear")
+    jobs = jobs[:3] + [circ, dod] + jobs[3:]
+    show_case("batch linear order", unbatched)
+    rc, errs, zs, sts = run_batch(ctx, jobs, unbatched=unbatched)
+    assert errs[3] == oracle.EINVAL and errs[4] == oracle.EINVAL and rc == oracle.EINVAL
+    for i, j in enumerate(jobs):
+        if i in (3, 4):
+            continue
+        assert errs[i] == 0 and sts[i] == 0
+        assert np.array_equal(zs[i], oracle.extract(j.kind, j.x, j.y, j.n, j.m, j.seed_order)[1])
+
+
 def test_batched_workload_at_its_sizes():
     """The batched workload exactly as the benchmark runs it: 4096 Toeplitz/Circulant
     blocks, n log-uniform in [2^10, 2^22], m = n/2, one extract_batch replayed from a
